@@ -1,0 +1,314 @@
+"""Pins for the CPU oracle, each against something other than the oracle itself:
+brute-force sums, numpy's FFT, closed forms, invariants, statistics the
+generator's recipe fixes, and hand-built cases.  CPU only."""
+import math
+
+import numpy as np
+import pytest
+import torch
+from numpy.polynomial.hermite_e import hermegauss
+from scipy.special import ndtr
+
+import synth
+
+
+# ---------------------------------------------------------------- unpacking
+
+def test_unpack_every_byte(orc):
+    """All 256 byte values: low nibble is the even sample, two's complement."""
+    b = np.arange(256, dtype=np.uint8)
+    x = orc.unpack(b).reshape(256, 2)
+    for v in range(256):
+        lo, hi = v & 0xF, v >> 4
+        assert x[v, 0] == (lo if lo < 8 else lo - 16)
+        assert x[v, 1] == (hi if hi < 8 else hi - 16)
+    assert x.min() == -8 and x.max() == 7
+
+
+def test_pack_unpack_round_trip(orc):
+    g = torch.Generator().manual_seed(5)
+    x = torch.randint(-8, 8, (3, 5, 64), generator=g, dtype=torch.int8)
+    p = synth.pack(x).numpy()
+    assert p.shape == (3, 5, 32)
+    np.testing.assert_array_equal(orc.unpack(p), x.numpy().ravel())
+
+
+# ---------------------------------------------------------------- transforms
+
+@pytest.mark.parametrize("n", [2, 8, 16, 32, 64])
+def test_fft_matches_brute_force_dft(orc, n):
+    rng = np.random.default_rng(n)
+    z = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    j = np.arange(n)
+    dft = np.array([np.sum(z * np.exp(-2j * np.pi * k * j / n)) for k in range(n)])
+    got = orc.fft(z)
+    assert np.max(np.abs(got - dft)) <= 1e-12 * np.max(np.abs(dft))
+
+
+@pytest.mark.parametrize("n", [256, 512, 1024, 2048])
+def test_fft_matches_numpy(orc, n):
+    rng = np.random.default_rng(n + 1)
+    z = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    ref = np.fft.fft(z)
+    assert np.max(np.abs(orc.fft(z) - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_fft_real_parseval_and_hermitian(orc):
+    rng = np.random.default_rng(7)
+    for two_k in (16, 512, 2048):
+        x = rng.integers(-8, 8, two_k).astype(np.float64)
+        X = orc.fft_real(x)
+        K = two_k // 2
+        # real input: X[2K-k] = conj(X[k])
+        np.testing.assert_allclose(X[1:][::-1], np.conj(X[1:]), rtol=0, atol=1e-9)
+        # Parseval over the half spectrum that is kept plus the Nyquist bin
+        e_time = np.sum(x * x)
+        e_freq = (abs(X[0]) ** 2 + 2 * np.sum(np.abs(X[1:K]) ** 2) + abs(X[K]) ** 2) / two_k
+        assert abs(e_time - e_freq) <= 1e-9 * e_time
+
+
+def test_spectra_integer_bins(orc):
+    """DC is the sample sum; bin K/2 is sum x[n](-i)^n: both Gaussian integers."""
+    g = torch.Generator().manual_seed(11)
+    S, N, K = 4, 3, 256
+    x = torch.randint(-8, 8, (S, N, 2 * K), generator=g, dtype=torch.int8)
+    spec = orc.spectra(synth.pack(x).numpy(), S, N, K)
+    xn = x.numpy().astype(np.int64)
+    dc = xn.sum(axis=2)
+    np.testing.assert_allclose(spec[:, :, 0].real, dc, rtol=0, atol=1e-9)
+    np.testing.assert_allclose(spec[:, :, 0].imag, 0, atol=1e-9)
+    ph = np.array([1, -1j, -1, 1j])[np.arange(2 * K) % 4]
+    half = (xn * ph).sum(axis=2)
+    np.testing.assert_allclose(spec[:, :, K // 2], half, rtol=0, atol=1e-8)
+
+
+def test_spectra_match_numpy_rfft(orc):
+    g = torch.Generator().manual_seed(12)
+    for K in (128, 256, 512, 1024):
+        S, N = 2, 3
+        x = torch.randint(-8, 8, (S, N, 2 * K), generator=g, dtype=torch.int8)
+        spec = orc.spectra(synth.pack(x).numpy(), S, N, K)
+        ref = np.fft.rfft(x.numpy().astype(np.float64), axis=2)[:, :, :K]
+        assert np.max(np.abs(spec - ref)) <= 1e-11 * np.max(np.abs(ref))
+
+
+def test_spectra_tone_lands_in_its_bin(orc):
+    """A common tone at integer bin k0 peaks every auto spectrum at k0 (this
+    also fixes the nibble order: swapped samples would move the peak)."""
+    for two_k, k0 in ((512, 77), (256, 21), (1024, 300)):
+        r = synth.recipe_tone(N=3, two_k=two_k, tone_bin=k0, tone_amp=0.5, seed=2)
+        K = two_k // 2
+        p = synth.packed(r, 0, 32).numpy()
+        vis = orc.cmac_f64(orc.spectra(p, 32, 3, K))
+        for a in range(3):
+            auto = vis[orc.baseline_index(3, a, a)].real
+            assert int(np.argmax(auto[1:])) + 1 == k0
+
+
+# ---------------------------------------------------------------- X-stage
+
+def _brute_vis(spec):
+    S, N, K = spec.shape
+    out = np.zeros((N * (N + 1) // 2, K), dtype=np.complex128)
+    bl = 0
+    for a in range(N):
+        for b in range(a, N):
+            for k in range(K):
+                acc = 0j
+                for s in range(S):
+                    acc += spec[s, a, k] * np.conj(spec[s, b, k])
+                out[bl, k] = acc
+            bl += 1
+    return out
+
+
+def test_cmac_matches_brute_force(orc):
+    rng = np.random.default_rng(3)
+    spec = rng.standard_normal((5, 4, 6)) + 1j * rng.standard_normal((5, 4, 6))
+    np.testing.assert_allclose(orc.cmac_f64(spec), _brute_vis(spec), rtol=1e-13, atol=1e-12)
+
+
+def test_baseline_index_order(orc):
+    for N in (1, 2, 5, 44):
+        seen = []
+        for a in range(N):
+            for b in range(a, N):
+                seen.append(orc.baseline_index(N, a, b))
+        assert seen == list(range(N * (N + 1) // 2))
+
+
+def test_cmac_hermitian_autos_identical_zero(orc):
+    g = torch.Generator().manual_seed(21)
+    S, N, K = 16, 5, 64
+    x = torch.randint(-8, 8, (S, N, 2 * K), generator=g, dtype=torch.int8)
+    x[:, 3] = x[:, 1]                      # antenna 3 is a copy of antenna 1
+    x[:, 4] = 0                            # antenna 4 is dead
+    spec = orc.spectra(synth.pack(x).numpy(), S, N, K)
+    full = orc.cmac_f64(spec, full=True)
+    np.testing.assert_array_equal(full, np.conj(np.transpose(full, (1, 0, 2))))
+    for a in range(N):
+        assert np.all(full[a, a].imag == 0.0)
+        assert np.all(full[a, a].real >= 0.0)
+    np.testing.assert_array_equal(full[1, 3], full[1, 1])
+    np.testing.assert_array_equal(full[3, 3], full[1, 1])
+    assert np.all(full[4] == 0) and np.all(full[:, 4] == 0)
+    tri = orc.cmac_f64(spec)
+    for a in range(N):
+        for b in range(a, N):
+            np.testing.assert_array_equal(tri[orc.baseline_index(N, a, b)], full[a, b])
+
+
+def test_cmac_linear_in_time(orc):
+    rng = np.random.default_rng(4)
+    spec = rng.standard_normal((20, 3, 8)) + 1j * rng.standard_normal((20, 3, 8))
+    whole = orc.cmac_f64(spec)
+    parts = orc.cmac_f64(spec[:7]) + orc.cmac_f64(spec[7:])
+    np.testing.assert_allclose(whole, parts, rtol=1e-12, atol=1e-12)
+
+
+def _quantised_correlation(sigma, rho):
+    """Expected correlation of Q(X_a), Q(X_b) with X = sigma*(sqrt(1-rho) g + sqrt(rho) c),
+    Q = clamp(rint(.), -8, 7): E over c of the conditional mean (a 1-D quadrature)."""
+    levels = np.arange(-8, 8, dtype=np.float64)
+    edges = np.concatenate(([-np.inf], levels[1:] - 0.5, [np.inf]))
+    s = sigma * math.sqrt(1.0 - rho)
+    c, w = hermegauss(160)
+    w = w / w.sum()
+    mu = sigma * math.sqrt(rho) * c
+    cdf = ndtr((edges[None, :] - mu[:, None]) / s)
+    p = np.diff(cdf, axis=1)                       # P(Q = level | c)
+    m1 = p @ levels                                 # E[Q | c]
+    m2 = p @ (levels ** 2)                          # E[Q^2 | c]
+    eq = np.sum(w * m1)
+    cross = np.sum(w * m1 * m1)                     # E[Q_a Q_b] (independent given c)
+    var = np.sum(w * m2) - eq ** 2
+    return (cross - eq ** 2) / var
+
+
+@pytest.mark.parametrize("rho", [0.05, 0.3])
+def test_correlation_coefficient_of_common_signal(orc, rho):
+    S, N, two_k = 2048, 6, 512
+    K = two_k // 2
+    r = synth.recipe_plain(N=N, two_k=two_k, rho=rho, seed=9)
+    vis = orc.correlate(synth.packed(r, 0, S).numpy(), S, N, K)
+    rho_q = _quantised_correlation(2.5, rho)
+    coef = []
+    for a in range(N):
+        for b in range(a + 1, N):
+            v = vis[orc.baseline_index(N, a, b), 1:]
+            va = vis[orc.baseline_index(N, a, a), 1:].real
+            vb = vis[orc.baseline_index(N, b, b), 1:].real
+            coef.append(v / np.sqrt(va * vb))
+    coef = np.array(coef)
+    se = 1.0 / math.sqrt(S * (K - 1))
+    assert abs(coef.real.mean() - rho_q) < 6 * se
+    assert abs(coef.imag.mean()) < 6 * se
+    # the gain of the 4-bit quantiser at sigma = 2.5 is close to, below, 1
+    assert 0.97 * rho < rho_q < rho
+
+
+def test_delay_phase_slope(orc):
+    """A common source seen with delay d_a = a samples gives
+    arg V_ab[k] = 2 pi k (b - a) / 2K."""
+    S, N, two_k = 512, 4, 256
+    K = two_k // 2
+    r = synth.Recipe(N=N, two_k=two_k, seed=4,
+                     sources=[synth.Source(rho=0.5, delay_per_antenna=1.0)])
+    vis = orc.correlate(synth.packed(r, 0, S).numpy(), S, N, K)
+    k = np.arange(1, K)
+    for a in range(N):
+        for b in range(a + 1, N):
+            phase = np.unwrap(np.angle(vis[orc.baseline_index(N, a, b), 1:]))
+            slope = np.polyfit(k, phase, 1)[0]          # radians per bin
+            assert abs(slope * two_k / (2 * math.pi) - (b - a)) < 0.05
+
+
+def test_vis_single_matches_full_path(orc):
+    S, N, K = 12, 4, 128
+    r = synth.recipe_plain(N=N, two_k=2 * K, seed=1)
+    p = synth.packed(r, 0, S).numpy()
+    vis = orc.correlate(p, S, N, K)
+    for (a, b, k) in ((0, 0, 0), (0, 3, 5), (1, 2, 64), (2, 3, 127), (3, 3, 99)):
+        got = orc.vis_single(p, S, N, K, a, b, k)
+        ref = vis[orc.baseline_index(N, a, b), k]
+        assert abs(got - ref) <= 1e-9 * max(1.0, abs(ref))
+
+
+# ---------------------------------------------------------------- int8 form
+
+def test_quantise_rounding_and_saturation(orc):
+    """Ties go to even, values saturate symmetrically at +-127."""
+    xs = np.array([0.5, 1.5, 2.5, -0.5, -1.5, -2.5, 126.5, 127.4, 200.0, -200.0, 3.49, -3.51])
+    want = np.array([0, 2, 2, 0, -2, -2, 126, 127, 127, -127, 3, -4])
+    spec = xs.reshape(-1, 1, 1) + 0j
+    q = orc.quantise(spec, np.ones((1, 1), dtype=np.float32))
+    np.testing.assert_array_equal(q[:, 0, 0, 0], want)
+    np.testing.assert_array_equal(q[:, 0, 0, 1], 0)
+    q = orc.quantise(1j * spec, np.ones((1, 1), dtype=np.float32))
+    np.testing.assert_array_equal(q[:, 0, 0, 1], want)
+    # scale applied before rounding, in float
+    q = orc.quantise(np.array([[[1.25 + 0.75j]]]), np.full((1, 1), 2.0, dtype=np.float32))
+    np.testing.assert_array_equal(q[0, 0, 0], [2, 2])
+
+
+def test_scales_follow_rms_rule(orc):
+    """Constant-magnitude spectra: rms is known, so sc = 127 / (4 rms)."""
+    S, N, K = 10, 2, 3
+    spec = np.zeros((S, N, K), dtype=np.complex128)
+    spec[:, 0, :] = 3.0 + 4.0j          # |x|^2 = 25 -> per-component rms 5/sqrt(2)
+    spec[:, 1, 0] = 2.0                  # |x|^2 = 4  -> rms sqrt(2)
+    spec[5:, 1, 1] = 100.0               # outside a window of 5: zero power inside
+    sc = orc.scales(spec, W=5)
+    np.testing.assert_allclose(sc[0], 127.0 / (4 * 5 / math.sqrt(2)), rtol=1e-7)
+    np.testing.assert_allclose(sc[1, 0], 127.0 / (4 * math.sqrt(2)), rtol=1e-7)
+    assert sc[1, 1] == 1.0 and sc[1, 2] == 1.0
+
+
+def test_int8_saturation_matches_gaussian_tail(orc):
+    """With full scale at 4 rms, a Gaussian component saturates with probability
+    P(|z| > 4 * 127.5 / 127)."""
+    S, N, K = 1024, 4, 256
+    r = synth.recipe_plain(N=N, two_k=2 * K, seed=6)
+    spec = orc.spectra(synth.packed(r, 0, S).numpy(), S, N, K)
+    sc = orc.scales(spec, W=S)
+    q = orc.quantise(spec[:, :, 1:], sc[:, 1:])
+    frac = np.mean(np.abs(q) == 127)
+    p = 2 * (1 - ndtr(4 * 127.5 / 127))
+    n = q.size
+    assert abs(frac - p) < 6 * math.sqrt(p / n) + 1e-6
+
+
+def test_cmac_i64_exact(orc):
+    g = torch.Generator().manual_seed(8)
+    S, N, K = 9, 4, 5
+    q = torch.randint(-127, 128, (S, N, K, 2), generator=g, dtype=torch.int8).numpy()
+    vi = orc.cmac_i64(q)
+    spec = q[..., 0].astype(np.float64) + 1j * q[..., 1].astype(np.float64)
+    brute = _brute_vis(spec)
+    np.testing.assert_array_equal(vi[..., 0], brute.real.astype(np.int64))
+    np.testing.assert_array_equal(vi[..., 1], brute.imag.astype(np.int64))
+    full = orc.cmac_i64(q, full=True)
+    for a in range(N):
+        assert np.all(full[a, a, :, 1] == 0)
+
+
+def test_cmac_i64_extreme_values_exact(orc):
+    """Worst case magnitude: every component at +-127 over many spectra; the
+    int64 sums are exact and equal float64 on the same integers."""
+    S, N, K = 4096, 2, 2
+    q = np.full((S, N, K, 2), 127, dtype=np.int8)
+    q[:, 1, :, 1] = -127
+    vi = orc.cmac_i64(q)
+    assert vi[0, 0, 0] == 2 * S * 127 * 127
+    assert vi[1, 0, 0] == 0 and vi[1, 0, 1] == 2 * S * 127 * 127
+    spec = q[..., 0].astype(np.float64) + 1j * q[..., 1].astype(np.float64)
+    vf = orc.cmac_f64(spec)
+    np.testing.assert_array_equal(vi[..., 0], vf.real.astype(np.int64))
+    np.testing.assert_array_equal(vi[..., 1], vf.imag.astype(np.int64))
+
+
+def test_oracle_rejects_bad_arguments(orc):
+    with pytest.raises(ValueError):
+        orc.fft(np.zeros(12, dtype=np.complex128))
+    with pytest.raises(ValueError):
+        orc.spectra(np.zeros(2 * 3 * 100, dtype=np.uint8), 2, 3, 100)
