@@ -1,0 +1,191 @@
+/*
+ * corr.h -- C ABI of the MI355X FX spectral correlator (libcorr.so).
+ *
+ * The library computes, for N antennas of 4-bit real samples, the cross power
+ * spectra of every antenna pair in every channel (Prasad & Subrahmanya,
+ * Section 1): each 2K-sample block of each antenna is Fourier transformed into
+ * K channels (the F-stage), the spectra are turned channel-major, and every
+ * pair is cross-multiplied and accumulated over the spectra of an integration
+ * (the X-stage).  Each time tile's partial result is added into a float64
+ * integration buffer.
+ *
+ * Conventions common to every entry point:
+ *   - Input frames: byte layout [spectrum][antenna][K bytes]; one antenna
+ *     block holds 2K samples, two per byte, two's-complement nibbles -8..7,
+ *     the low nibble being the earlier sample (Section 2.2: one frame carries
+ *     contiguous samples of all elements and is one FFT block; Section 1:
+ *     4-bit quantisation).
+ *   - Transform: forward, unnormalised, no window (Section 4); channels are
+ *     bins 0..K-1 of the 2K-point real transform (the Nyquist bin is dropped).
+ *   - Visibilities: V[a,b,k] = sum_s X[s,a,k] * conj(X[s,b,k]) for a <= b,
+ *     autos included.  Baseline index bl(a,b) = a*N - a*(a-1)/2 + (b-a)
+ *     (upper triangle, row-major).  Output arrays are [baseline][channel]
+ *     complex values, real part first.  The imaginary part of an auto is
+ *     exactly 0.
+ *   - Ownership: the caller owns every buffer it passes in; device input must
+ *     stay valid until the stream has passed the call that consumed it.  The
+ *     library owns its scratch (spectra chunk, partials, integration buffer,
+ *     scales, twiddles) and frees it in corr_destroy.
+ *   - Errors: functions return CORR_OK (0) or a negative status; creators
+ *     return NULL.  corr_last_error() gives a thread-local message.  An
+ *     asynchronous GPU error surfaces as CORR_EHIP on a later call.
+ *   - Threading: a handle is not thread-safe; use one handle per stream.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ */
+#ifndef CORR_H
+#define CORR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct corr_ctx *corr_handle;
+
+enum corr_status {
+    CORR_OK = 0,
+    CORR_EINVAL = -1, /* bad argument: size, pointer, mode, job index */
+    CORR_ENOMEM = -2, /* device or host allocation failed */
+    CORR_EHIP = -3,   /* the HIP runtime reported an error */
+    CORR_ESTATE = -4  /* call not allowed in the handle's current state */
+};
+
+/* Arithmetic of the X-stage.  FP32: float spectra, float products and sums.
+ * FP16: spectra rounded to half (ties to even), float accumulation.  INT8:
+ * spectra requantised per antenna and channel (Section 4's conversion to a
+ * short integer type with prescaling, here to 8 bits), exact int32 sums.  */
+enum corr_precision { CORR_FP32 = 0, CORR_FP16 = 1, CORR_INT8 = 2 };
+
+/* Limits checked by corr_create.  */
+#define CORR_MAX_ANTENNAS 512
+#define CORR_MIN_CHANNELS 128
+#define CORR_MAX_CHANNELS 1024
+/* int8 calibration window: the first min(n_spectra, CORR_CALIB_SPECTRA)
+ * spectra of each integration set the scales of that integration.  */
+#define CORR_CALIB_SPECTRA 1024
+
+/* Create a correlator for N antennas, K channels (a 2K-point transform;
+ * Section 1 counts K complex multipliers per 2K-point transform), and
+ * integrations of n_spectra spectra.  2 <= N <= CORR_MAX_ANTENNAS; K a power
+ * of two in [CORR_MIN_CHANNELS, CORR_MAX_CHANNELS]; 1 <= n_spectra <= 2^24
+ * (int8 also needs n_spectra <= 65536 so every int32 partial is exact).
+ * Allocates all device scratch on the current HIP device.  Precision starts
+ * as CORR_FP32.  NULL on error.  */
+corr_handle corr_create(int N, int K, int n_spectra);
+
+/* Select the X-stage arithmetic (enum corr_precision).  Allowed only before
+ * the first corr_process / corr_process_spectra, else CORR_ESTATE.  */
+int corr_set_precision(corr_handle h, int mode);
+
+/* Tile and chunk choices (written by the autotuner; 0 keeps the default).
+ *   chunk_spectra: spectra per F->X chunk (multiple of 64).
+ *   x_splits:      time splits of one chunk in the X-stage (partials per
+ *                  channel per chunk; 1..64).
+ *   f_group:       antennas per F-stage tile (2, 4 or 8).
+ * Allowed only before the first process call, else CORR_ESTATE.  */
+typedef struct {
+    int chunk_spectra;
+    int x_splits;
+    int f_group;
+} corr_tiles;
+int corr_set_tiles(corr_handle h, const corr_tiles *t);
+int corr_get_tiles(corr_handle h, corr_tiles *t);
+
+/* Correlate one integration.  packed_samples: DEVICE pointer to
+ * n_spectra*N*K bytes in the frame layout above.  Enqueues the whole F + X +
+ * dump sequence on `stream` and returns without waiting; the result is added
+ * into the handle's float64 integration buffer.  For INT8 the scales are
+ * recomputed from this call's calibration window first.  */
+int corr_process(corr_handle h, const void *packed_samples, void *stream);
+
+/* Read the integration buffer and clear it.  Waits for `the last stream`
+ * used with this handle.  out: HOST pointer to nb*K*2 floats, nb =
+ * N(N+1)/2, layout [baseline][channel][re, im], in the units of the
+ * unnormalised transform (INT8 values are divided by s_a*s_b, the two
+ * antennas' scales).  CORR_ESTATE if nothing was processed since the last
+ * read.  */
+int corr_read_cps(corr_handle h, float *out);
+
+/* As corr_read_cps but the float64 buffer as it is: for INT8 the exact
+ * integer sums in quantised units.  out: HOST pointer to nb*K*2 doubles.  */
+int corr_read_cps_raw(corr_handle h, double *out);
+
+/* Asynchronous read: enqueue on `stream` a copy of the raw float64 buffer
+ * (layout as corr_read_cps_raw) into dst -- a DEVICE pointer, or pinned host
+ * memory -- then clear the buffer.  Does not wait.  */
+int corr_read_cps_async(corr_handle h, double *dst, void *stream);
+
+/* INT8 only: the scales [N][K] (float) used by the last integration.
+ * out: HOST pointer.  Waits for the handle's stream.  */
+int corr_read_scales(corr_handle h, float *out);
+
+/* Bytes of spectra in the library layout for n_spectra spectra (the size of
+ * the buffer corr_process_spectra reads and corr_debug_read_spectra writes),
+ * or 0 on error.  Layout: records of 16 bytes indexed
+ * [channel][tq][antenna_pad], tq = t / TG, antenna_pad = N rounded up to 16,
+ * tq padded to a multiple of 4; a record holds TG consecutive spectra of one
+ * antenna and channel as [re x TG][im x TG] in the precision's type (float,
+ * TG=2; half, TG=4; int8, TG=8).  Padding records and antennas are zero.  */
+size_t corr_spectra_bytes(corr_handle h, int n_spectra);
+
+/* X-stage + dump only, on n_spectra spectra already in the library layout
+ * (DEVICE pointer, corr_spectra_bytes(h, n_spectra) bytes).  Adds into the
+ * integration buffer like corr_process; INT8 spectra are taken as given.  */
+int corr_process_spectra(corr_handle h, const void *spectra, int n_spectra, void *stream);
+
+/* Copy the spectra of the last chunk the F-stage produced (library layout)
+ * to HOST memory `out` (corr_spectra_bytes(h, *n_spectra) bytes; pass
+ * out = NULL to query *n_spectra only).  Waits for the stream.  For tests.  */
+int corr_debug_read_spectra(corr_handle h, void *out, int *n_spectra);
+
+/* Counters and, when timing is on, per-stage GPU time summed over the calls
+ * since the last read (HIP events on the caller's stream).  */
+typedef struct {
+    int64_t spectra_accumulated; /* spectra in the integration buffer */
+    int64_t int8_saturated;      /* components clamped to +-127 (INT8) */
+    int precision;
+    int chunk_spectra, x_splits, f_group;
+    double ms_calib, ms_f, ms_x, ms_dump; /* 0 unless timing is on */
+    int64_t launches_f, launches_x;
+} corr_stats;
+int corr_get_stats(corr_handle h, corr_stats *out);
+/* on != 0: record HIP events around each stage (adds a little launch work). */
+int corr_enable_timing(corr_handle h, int on);
+
+/* Wait for the stream, free everything.  NULL-safe.  */
+void corr_destroy(corr_handle h);
+
+/* Thread-local message of the last failure ("" if none).  */
+const char *corr_last_error(void);
+
+/* ----------------------------------------------------------------- batch
+ * Many independent correlations of different N and K run as one persistent
+ * kernel launch, replayed as a captured HIP graph (no counterpart in the
+ * paper; the closest is Section 3.1's replication of core pairs to absorb
+ * more elements or bandwidth).  Each job follows the single-job semantics
+ * above.  */
+typedef struct {
+    int N;
+    int K;
+    int n_spectra;
+    int precision;
+} corr_job;
+
+/* Create a batch of n_jobs (1..64) jobs with the same limits as corr_create.
+ * Tile choices come from the autotuner's table (corr_batch_set_tiles), else
+ * defaults.  NULL on error.  */
+corr_handle corr_batch_create(const corr_job *jobs, int n_jobs);
+int corr_batch_set_tiles(corr_handle b, int job, const corr_tiles *t);
+/* packed_per_job: HOST array of n_jobs DEVICE pointers, job j's frames as in
+ * corr_process.  Enqueues one graph launch on `stream`.  */
+int corr_batch_process(corr_handle b, const void *const *packed_per_job, void *stream);
+int corr_batch_read_cps(corr_handle b, int job, float *out);
+int corr_batch_read_cps_raw(corr_handle b, int job, double *out);
+int corr_batch_read_scales(corr_handle b, int job, float *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CORR_H */

@@ -1,0 +1,359 @@
+"""MI355X FX spectral correlator: Python binding of libcorr.so.
+
+Module-level functions carry the C ABI's names (include/corr.h) and only
+marshal arguments; every step of the correlator runs in the library's HIP
+kernels.  PyTorch supplies device memory and streams.  If libcorr.so is not
+built, the first call raises -- there is no CPU fallback.
+
+    import paper_1102_0148_amd as corr
+    c = corr.Correlator(N=44, K=256, n_spectra=1024)     # FP32 path
+    c.process(packed_uint8_cuda_tensor)                  # [S][N][K] bytes
+    vis = c.read_cps()                                   # complex64 [nb][K]
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcorr.so")
+
+CORR_OK, CORR_EINVAL, CORR_ENOMEM, CORR_EHIP, CORR_ESTATE = 0, -1, -2, -3, -4
+CORR_FP32, CORR_FP16, CORR_INT8 = 0, 1, 2
+CORR_CALIB_SPECTRA = 1024
+PRECISIONS = {"fp32": CORR_FP32, "fp16": CORR_FP16, "int8": CORR_INT8}
+
+# Every symbol include/corr.h declares.
+EXPORTS = (
+    "corr_create", "corr_set_precision", "corr_set_tiles", "corr_get_tiles", "corr_process",
+    "corr_read_cps", "corr_read_cps_raw", "corr_read_cps_async", "corr_read_scales",
+    "corr_spectra_bytes", "corr_process_spectra", "corr_debug_read_spectra", "corr_get_stats",
+    "corr_enable_timing", "corr_destroy", "corr_last_error", "corr_batch_create",
+    "corr_batch_set_tiles", "corr_batch_process", "corr_batch_read_cps",
+    "corr_batch_read_cps_raw", "corr_batch_read_scales",
+)
+
+
+class CorrError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"[{code}] {message}")
+        self.code = code
+
+
+class corr_tiles(ctypes.Structure):
+    _fields_ = [("chunk_spectra", ctypes.c_int), ("x_splits", ctypes.c_int), ("f_group", ctypes.c_int)]
+
+
+class corr_stats(ctypes.Structure):
+    _fields_ = [("spectra_accumulated", ctypes.c_int64), ("int8_saturated", ctypes.c_int64),
+                ("precision", ctypes.c_int), ("chunk_spectra", ctypes.c_int),
+                ("x_splits", ctypes.c_int), ("f_group", ctypes.c_int),
+                ("ms_calib", ctypes.c_double), ("ms_f", ctypes.c_double),
+                ("ms_x", ctypes.c_double), ("ms_dump", ctypes.c_double),
+                ("launches_f", ctypes.c_int64), ("launches_x", ctypes.c_int64)]
+
+
+class corr_job(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int), ("K", ctypes.c_int), ("n_spectra", ctypes.c_int),
+                ("precision", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libcorr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1102_0148_amd.build` "
+                           "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    P, I, I64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
+    sigs = {
+        "corr_create": (P, [I, I, I]),
+        "corr_set_precision": (I, [P, I]),
+        "corr_set_tiles": (I, [P, ctypes.POINTER(corr_tiles)]),
+        "corr_get_tiles": (I, [P, ctypes.POINTER(corr_tiles)]),
+        "corr_process": (I, [P, P, P]),
+        "corr_read_cps": (I, [P, P]),
+        "corr_read_cps_raw": (I, [P, P]),
+        "corr_read_cps_async": (I, [P, P, P]),
+        "corr_read_scales": (I, [P, P]),
+        "corr_spectra_bytes": (ctypes.c_size_t, [P, I]),
+        "corr_process_spectra": (I, [P, P, I, P]),
+        "corr_debug_read_spectra": (I, [P, P, ctypes.POINTER(I)]),
+        "corr_get_stats": (I, [P, ctypes.POINTER(corr_stats)]),
+        "corr_enable_timing": (I, [P, I]),
+        "corr_destroy": (None, [P]),
+        "corr_last_error": (ctypes.c_char_p, []),
+        "corr_batch_create": (P, [ctypes.POINTER(corr_job), I]),
+        "corr_batch_set_tiles": (I, [P, I, ctypes.POINTER(corr_tiles)]),
+        "corr_batch_process": (I, [P, ctypes.POINTER(P), P]),
+        "corr_batch_read_cps": (I, [P, I, P]),
+        "corr_batch_read_cps_raw": (I, [P, I, P]),
+        "corr_batch_read_scales": (I, [P, I, P]),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def corr_last_error() -> str:
+    return load().corr_last_error().decode()
+
+
+def _check(rc: int) -> int:
+    if rc != CORR_OK:
+        raise CorrError(rc, corr_last_error())
+    return rc
+
+
+def _handle(h):
+    if not h:
+        raise CorrError(CORR_EINVAL, corr_last_error() or "creation failed")
+    return h
+
+
+# ------------------------------------------------ C ABI, one wrapper per call
+
+def corr_create(N: int, K: int, n_spectra: int):
+    return _handle(load().corr_create(N, K, n_spectra))
+
+
+def corr_set_precision(h, mode: int):
+    return _check(load().corr_set_precision(h, mode))
+
+
+def corr_set_tiles(h, chunk_spectra=0, x_splits=0, f_group=0):
+    t = corr_tiles(chunk_spectra, x_splits, f_group)
+    return _check(load().corr_set_tiles(h, ctypes.byref(t)))
+
+
+def corr_get_tiles(h) -> dict:
+    t = corr_tiles()
+    _check(load().corr_get_tiles(h, ctypes.byref(t)))
+    return {"chunk_spectra": t.chunk_spectra, "x_splits": t.x_splits, "f_group": t.f_group}
+
+
+def corr_process(h, packed_ptr: int, stream: int = 0):
+    return _check(load().corr_process(h, packed_ptr, stream))
+
+
+def corr_read_cps(h, out_ptr: int):
+    return _check(load().corr_read_cps(h, out_ptr))
+
+
+def corr_read_cps_raw(h, out_ptr: int):
+    return _check(load().corr_read_cps_raw(h, out_ptr))
+
+
+def corr_read_cps_async(h, dst_ptr: int, stream: int = 0):
+    return _check(load().corr_read_cps_async(h, dst_ptr, stream))
+
+
+def corr_read_scales(h, out_ptr: int):
+    return _check(load().corr_read_scales(h, out_ptr))
+
+
+def corr_spectra_bytes(h, n_spectra: int) -> int:
+    return int(load().corr_spectra_bytes(h, n_spectra))
+
+
+def corr_process_spectra(h, spectra_ptr: int, n_spectra: int, stream: int = 0):
+    return _check(load().corr_process_spectra(h, spectra_ptr, n_spectra, stream))
+
+
+def corr_debug_read_spectra(h, out_ptr: Optional[int]) -> int:
+    n = ctypes.c_int(0)
+    _check(load().corr_debug_read_spectra(h, out_ptr, ctypes.byref(n)))
+    return n.value
+
+
+def corr_get_stats(h) -> dict:
+    s = corr_stats()
+    _check(load().corr_get_stats(h, ctypes.byref(s)))
+    return {name: getattr(s, name) for name, _ in corr_stats._fields_}
+
+
+def corr_enable_timing(h, on: bool):
+    return _check(load().corr_enable_timing(h, int(bool(on))))
+
+
+def corr_destroy(h):
+    if h:
+        load().corr_destroy(h)
+
+
+def corr_batch_create(jobs):
+    arr = (corr_job * len(jobs))(*[corr_job(*j) for j in jobs])
+    return _handle(load().corr_batch_create(arr, len(jobs)))
+
+
+def corr_batch_set_tiles(b, job: int, chunk_spectra=0, x_splits=0, f_group=0):
+    t = corr_tiles(chunk_spectra, x_splits, f_group)
+    return _check(load().corr_batch_set_tiles(b, job, ctypes.byref(t)))
+
+
+def corr_batch_process(b, packed_ptrs, stream: int = 0):
+    arr = (ctypes.c_void_p * len(packed_ptrs))(*packed_ptrs)
+    return _check(load().corr_batch_process(b, arr, stream))
+
+
+def corr_batch_read_cps(b, job: int, out_ptr: int):
+    return _check(load().corr_batch_read_cps(b, job, out_ptr))
+
+
+def corr_batch_read_cps_raw(b, job: int, out_ptr: int):
+    return _check(load().corr_batch_read_cps_raw(b, job, out_ptr))
+
+
+def corr_batch_read_scales(b, job: int, out_ptr: int):
+    return _check(load().corr_batch_read_scales(b, job, out_ptr))
+
+
+# ------------------------------------------------ torch-facing convenience
+
+def _stream(stream) -> int:
+    import torch
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _np_ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+def n_baselines(N: int) -> int:
+    return N * (N + 1) // 2
+
+
+class Correlator:
+    """One correlation (N antennas, K channels, n_spectra per integration)."""
+
+    def __init__(self, N: int, K: int, n_spectra: int, precision="fp32", tiles: Optional[dict] = None):
+        self.N, self.K, self.S = N, K, n_spectra
+        self.nb = n_baselines(N)
+        self.h = corr_create(N, K, n_spectra)
+        try:
+            mode = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+            corr_set_precision(self.h, mode)
+            self.precision = mode
+            if tiles:
+                corr_set_tiles(self.h, **tiles)
+        except Exception:
+            self.close()
+            raise
+
+    def close(self):
+        if getattr(self, "h", None):
+            corr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def tiles(self) -> dict:
+        return corr_get_tiles(self.h)
+
+    def process(self, packed, stream=None):
+        """packed: uint8 CUDA tensor holding n_spectra*N*K bytes."""
+        assert packed.is_cuda and packed.numel() == self.S * self.N * self.K
+        corr_process(self.h, packed.data_ptr(), _stream(stream))
+
+    def spectra_bytes(self, n_spectra: int) -> int:
+        return corr_spectra_bytes(self.h, n_spectra)
+
+    def process_spectra(self, spectra, n_spectra: int, stream=None):
+        """spectra: CUDA tensor in the library's record layout."""
+        assert spectra.is_cuda and spectra.numel() * spectra.element_size() >= self.spectra_bytes(n_spectra)
+        corr_process_spectra(self.h, spectra.data_ptr(), n_spectra, _stream(stream))
+
+    def read_cps_raw(self) -> np.ndarray:
+        out = np.empty((self.nb, self.K, 2), dtype=np.float64)
+        corr_read_cps_raw(self.h, _np_ptr(out))
+        return out
+
+    def read_cps(self) -> np.ndarray:
+        out = np.empty((self.nb, self.K, 2), dtype=np.float32)
+        corr_read_cps(self.h, _np_ptr(out))
+        return out[..., 0] + 1j * out[..., 1]
+
+    def read_cps_async(self, dst, stream=None):
+        """dst: float64 CUDA tensor with nb*K*2 elements."""
+        assert dst.numel() == self.nb * self.K * 2
+        corr_read_cps_async(self.h, dst.data_ptr(), _stream(stream))
+
+    def read_scales(self) -> np.ndarray:
+        out = np.empty((self.N, self.K), dtype=np.float32)
+        corr_read_scales(self.h, _np_ptr(out))
+        return out
+
+    def debug_read_spectra(self):
+        n = corr_debug_read_spectra(self.h, None)
+        out = np.empty(self.spectra_bytes(n), dtype=np.uint8)
+        corr_debug_read_spectra(self.h, _np_ptr(out))
+        return out, n
+
+    def stats(self) -> dict:
+        return corr_get_stats(self.h)
+
+    def enable_timing(self, on: bool = True):
+        corr_enable_timing(self.h, on)
+
+
+# ------------------------------------------------ record layout (host side)
+
+def record_times(precision: int) -> int:
+    return {CORR_FP32: 2, CORR_FP16: 4, CORR_INT8: 8}[precision]
+
+
+def spectra_to_records(spec: np.ndarray, precision: int) -> np.ndarray:
+    """Lay out spectra [S][N][K] (complex for fp32/fp16; int8 [S][N][K][2] for
+    int8) as the library's records [K][tq][a_pad][re x TG | im x TG] bytes."""
+    tg = record_times(precision)
+    if precision == CORR_INT8:
+        S, N, K, _ = spec.shape
+        re, im = spec[..., 0], spec[..., 1]
+        dt = np.int8
+    else:
+        S, N, K = spec.shape
+        re, im = spec.real, spec.imag
+        dt = np.float32 if precision == CORR_FP32 else np.float16
+    a_pad = (N + 15) // 16 * 16 if (N + 15) // 16 <= 6 else (N + 63) // 64 * 64
+    ntq = ((S + tg - 1) // tg + 3) // 4 * 4
+    out = np.zeros((K, ntq, a_pad, 2, tg), dtype=dt)
+    t = np.arange(S)
+    # advanced indices (t // tg, 0, t % tg) put the time axis first: [S][K][N]
+    out[:, t // tg, :N, 0, t % tg] = np.transpose(re, (0, 2, 1)).astype(dt)
+    out[:, t // tg, :N, 1, t % tg] = np.transpose(im, (0, 2, 1)).astype(dt)
+    return out.view(np.uint8).reshape(-1)
+
+
+def records_to_spectra(buf: np.ndarray, precision: int, N: int, K: int, S: int) -> np.ndarray:
+    """Inverse of spectra_to_records: complex64 [S][N][K] (fp32/fp16, as float)
+    or int8 [S][N][K][2] (int8)."""
+    tg = record_times(precision)
+    dt = {CORR_FP32: np.float32, CORR_FP16: np.float16, CORR_INT8: np.int8}[precision]
+    a_pad = (N + 15) // 16 * 16 if (N + 15) // 16 <= 6 else (N + 63) // 64 * 64
+    ntq = ((S + tg - 1) // tg + 3) // 4 * 4
+    rec = np.asarray(buf).view(dt).reshape(K, ntq, a_pad, 2, tg)
+    t = np.arange(S)
+    re = rec[:, t // tg, :N, 0, t % tg]      # [S][K][N]
+    im = rec[:, t // tg, :N, 1, t % tg]
+    re = np.transpose(re, (0, 2, 1))
+    im = np.transpose(im, (0, 2, 1))
+    if precision == CORR_INT8:
+        return np.stack([re, im], axis=-1)
+    return re.astype(np.float32) + 1j * im.astype(np.float32)

@@ -1,0 +1,94 @@
+// Integration-buffer kernels: the float64 dump of tile partials (Section 1:
+// the cross power spectra are accumulated to the required cadence), the int8
+// calibration scales, the read-out transpose and a plain fill.
+#include "corr_internal.h"
+
+namespace corr {
+namespace {
+
+// acc[e] += partial[0][e] + partial[1][e] + ... in this order, in float64.
+template <typename P>
+__global__ __launch_bounds__(256) void dump_kernel(const P *partial, double2 *acc, int nsplit,
+                                                   int64_t n) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n) return;
+    double2 v = acc[e];
+    for (int s = 0; s < nsplit; ++s) {
+        const P p = partial[(int64_t)s * n + e];
+        v.x += (double)p.x;
+        v.y += (double)p.y;
+    }
+    acc[e] = v;
+}
+
+// rms over the window per component: sqrt(P / (2W)); scale = 127 / (4 rms);
+// a channel with no power keeps scale 1.
+__global__ __launch_bounds__(256) void scales_kernel(const float *power, int nparts, int N, int a_pad,
+                                                     int K, int W, float *scales) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= N * K) return;
+    const int ant = e / K, c = e % K;
+    float p = 0.0f;
+    for (int i = 0; i < nparts; ++i) p += power[((int64_t)i * a_pad + ant) * K + c];
+    float sc = 1.0f;
+    if (p > 0.0f) {
+        const float rms = sqrtf(p / (2.0f * (float)W));
+        sc = 127.0f / (4.0f * rms);
+    }
+    scales[e] = sc;
+}
+
+// dst[bl][f] = acc[f][bl]; acc = 0
+__global__ __launch_bounds__(256) void finalize_kernel(double2 *acc, double2 *dst, int K, int nb) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)K * nb) return;
+    const int f = (int)(e / nb), bl = (int)(e % nb);
+    dst[(int64_t)bl * K + f] = acc[e];
+    acc[e] = make_double2(0.0, 0.0);
+}
+
+__global__ __launch_bounds__(256) void fill_zero_kernel(uint4 *p, int64_t n16) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += (int64_t)gridDim.x * 256)
+        p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+}  // namespace
+
+hipError_t launch_dump(int prec, const void *partial, double2 *acc, int nsplit, int K, int nb,
+                       hipStream_t st) {
+    const int64_t n = (int64_t)K * nb;
+    const int grid = (int)((n + 255) / 256);
+    if (prec == kINT8)
+        hipLaunchKernelGGL(dump_kernel<int2>, dim3(grid), dim3(256), 0, st,
+                           reinterpret_cast<const int2 *>(partial), acc, nsplit, n);
+    else
+        hipLaunchKernelGGL(dump_kernel<float2>, dim3(grid), dim3(256), 0, st,
+                           reinterpret_cast<const float2 *>(partial), acc, nsplit, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_scales(const float *power, int nparts, int N, int a_pad, int K, int W,
+                         float *scales, hipStream_t st) {
+    const int grid = (N * K + 255) / 256;
+    hipLaunchKernelGGL(scales_kernel, dim3(grid), dim3(256), 0, st, power, nparts, N, a_pad, K, W, scales);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(double2 *acc, double2 *dst, int K, int nb, hipStream_t st) {
+    const int64_t n = (int64_t)K * nb;
+    const int grid = (int)((n + 255) / 256);
+    hipLaunchKernelGGL(finalize_kernel, dim3(grid), dim3(256), 0, st, acc, dst, K, nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st) {
+    if (bytes % 16) return hipErrorInvalidValue;
+    const int64_t n16 = (int64_t)(bytes / 16);
+    if (n16 == 0) return hipSuccess;
+    int64_t grid = (n16 + 255) / 256;
+    if (grid > 4096) grid = 4096;
+    hipLaunchKernelGGL(fill_zero_kernel, dim3((int)grid), dim3(256), 0, st, reinterpret_cast<uint4 *>(p), n16);
+    return hipGetLastError();
+}
+
+}  // namespace corr

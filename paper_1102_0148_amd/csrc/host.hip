@@ -1,0 +1,643 @@
+// Host runtime of libcorr.so: the C ABI declared in include/corr.h.
+//
+// One handle owns the float64 integration buffer of one correlation and the
+// scratch of its F -> X -> dump sequence.  corr_process splits an
+// integration into chunks of spectra; for each chunk the F-stage writes
+// channel-major records, the X-stage writes per-split partial visibilities
+// and the dump kernel adds them into float64.  Everything is enqueued on the
+// caller's stream; nothing blocks until a read.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/corr.h"
+#include "corr_internal.h"
+
+using namespace corr;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(CORR_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(call, what)                         \
+    do {                                            \
+        hipError_t e_ = (call);                     \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+// (cos, sin) of 2 pi q / n with exact values at multiples of pi/4 and the
+// same octant reduction for both, so cos and sin agree bit for bit where they
+// should.
+void cos_sin_2pi(int64_t q, int64_t n, double *c, double *s) {
+    q %= n;
+    if (q < 0) q += n;
+    const double r = std::sqrt(0.5);
+    if ((q * 8) % n == 0) {
+        static const double cs[8][2] = {{1, 0}, {0, 0}, {0, 1}, {0, 0}, {-1, 0}, {0, 0}, {0, -1}, {0, 0}};
+        const int oct = (int)(q * 8 / n);
+        if (oct % 2 == 0) {
+            *c = cs[oct][0];
+            *s = cs[oct][1];
+        } else {
+            *c = (oct == 1 || oct == 7) ? r : -r;
+            *s = (oct == 1 || oct == 3) ? r : -r;
+        }
+        return;
+    }
+    const int quad = (int)(4 * q / n);
+    const int64_t rem4 = 4 * q - (int64_t)quad * n;  // 4 * (q - quad n/4), in (0, n)
+    const long double pi = 3.141592653589793238462643383279502884L;
+    long double c0, s0;
+    if (2 * rem4 < n) {  // angle below pi/4
+        const long double ang = 2.0L * pi * (long double)rem4 / (4.0L * n);
+        c0 = cosl(ang);
+        s0 = sinl(ang);
+    } else {
+        const long double ang = 2.0L * pi * (long double)(n - rem4) / (4.0L * n);
+        c0 = sinl(ang);
+        s0 = cosl(ang);
+    }
+    switch (quad) {
+        case 0: *c = (double)c0; *s = (double)s0; break;
+        case 1: *c = (double)-s0; *s = (double)c0; break;
+        case 2: *c = (double)-c0; *s = (double)-s0; break;
+        default: *c = (double)s0; *s = (double)-c0; break;
+    }
+}
+
+// W_n^j = exp(-2 pi i j / n) as float2
+float2 twiddle(int64_t j, int64_t n) {
+    double c, s;
+    cos_sin_2pi(j, n, &c, &s);
+    return make_float2((float)c, (float)-s);
+}
+
+struct Timer {
+    int stage;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct corr_ctx {
+    // shape
+    int N = 0, K = 0, S = 0, prec = kFP32;
+    int a_pad = 0, nb = 0;
+    int device = 0;
+    bool batch = false;
+    // plan
+    corr_tiles tiles{0, 0, 0};
+    bool planned = false, started = false;
+    int TG = 2, ntq_buf = 0;
+    int nblk = 0, rb = 0, n_diag = 0, n_off = 0;
+    // device buffers
+    uint4 *spec = nullptr;
+    size_t spec_bytes = 0;
+    void *partial = nullptr;
+    double2 *acc = nullptr;
+    double2 *stage = nullptr;
+    float2 *tw = nullptr;
+    float *scales = nullptr;
+    float *power = nullptr;
+    int2 *regions = nullptr;
+    unsigned long long *sat = nullptr;
+    // state
+    int64_t accumulated = 0;
+    int last_chunk = 0;
+    hipStream_t last_stream = nullptr;
+    bool timing = false;
+    double ms[4] = {0, 0, 0, 0};  // calib, F, X, dump
+    int64_t launches_f = 0, launches_x = 0;
+    std::vector<Timer> timers;
+    // batch
+    std::vector<corr_ctx *> jobs;
+};
+
+namespace {
+
+int check_shape(int N, int K, int S) {
+    if (N < 2 || N > CORR_MAX_ANTENNAS) return fail(CORR_EINVAL, "N=%d out of [2, %d]", N, CORR_MAX_ANTENNAS);
+    if (!is_pow2(K) || K < CORR_MIN_CHANNELS || K > CORR_MAX_CHANNELS)
+        return fail(CORR_EINVAL, "K=%d is not a power of two in [%d, %d]", K, CORR_MIN_CHANNELS,
+                    CORR_MAX_CHANNELS);
+    if (S < 1 || S > (1 << 24)) return fail(CORR_EINVAL, "n_spectra=%d out of [1, 2^24]", S);
+    return CORR_OK;
+}
+
+void free_ctx(corr_ctx *h) {
+    if (!h) return;
+    if (h->last_stream) hipStreamSynchronize(h->last_stream);
+    hipDeviceSynchronize();
+    for (auto &t : h->timers) {
+        hipEventDestroy(t.a);
+        hipEventDestroy(t.b);
+    }
+    void *bufs[] = {h->spec, h->partial, h->acc, h->stage, h->tw, h->scales, h->power, h->regions, h->sat};
+    for (void *p : bufs)
+        if (p) hipFree(p);
+    for (corr_ctx *j : h->jobs) free_ctx(j);
+    delete h;
+}
+
+int default_chunk(const corr_ctx *h) {
+    const int64_t per_spectrum = (int64_t)h->a_pad * h->K * (kRecordBytes / h->TG);
+    const int64_t cap_bytes = (int64_t)1 << 30;
+    int64_t c = std::max<int64_t>(64, cap_bytes / per_spectrum / 64 * 64);
+    c = std::min<int64_t>(c, round_up64(h->S, 64));
+    return (int)c;
+}
+
+int default_group(int K) { return K >= 1024 ? 4 : 8; }
+
+int n_regions(const corr_ctx *h) { return h->n_diag + h->n_off; }
+
+int default_splits(const corr_ctx *h) {
+    const int64_t waves_per_split = (int64_t)n_regions(h) * h->K;
+    int s = (int)((4096 + waves_per_split - 1) / waves_per_split);
+    s = std::max(1, std::min(64, s));
+    // fp32 / fp16 partials cover at most ~2048 spectra each
+    if (h->prec != kINT8) {
+        const int chunk = h->tiles.chunk_spectra;
+        s = std::max(s, std::min(64, (chunk + 2047) / 2048));
+    }
+    return s;
+}
+
+// Resolve tiles and allocate the precision-dependent scratch.
+int plan(corr_ctx *h) {
+    if (h->planned) return CORR_OK;
+    HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+    h->TG = record_times(h->prec);
+    if (h->tiles.chunk_spectra == 0) h->tiles.chunk_spectra = default_chunk(h);
+    if (h->tiles.f_group == 0) h->tiles.f_group = default_group(h->K);
+    if (h->tiles.x_splits == 0) h->tiles.x_splits = default_splits(h);
+    const int chunk = h->tiles.chunk_spectra;
+    h->ntq_buf = round_up((chunk + h->TG - 1) / h->TG, 4);
+    h->spec_bytes = (size_t)h->K * h->ntq_buf * h->a_pad * kRecordBytes;
+    HIP_TRY(hipMalloc(&h->spec, h->spec_bytes), "hipMalloc(spectra chunk)");
+    HIP_TRY(hipMemset(h->spec, 0, h->spec_bytes), "hipMemset(spectra chunk)");
+    HIP_TRY(hipMalloc(&h->partial, (size_t)h->tiles.x_splits * h->K * h->nb * 8), "hipMalloc(partials)");
+    if (h->prec == kINT8) {
+        const int W = std::min(h->S, CORR_CALIB_SPECTRA);
+        const int ntq_w = (W + 1) / 2;
+        const int nparts = (ntq_w + 31) / 32;
+        HIP_TRY(hipMalloc(&h->scales, (size_t)h->N * h->K * sizeof(float)), "hipMalloc(scales)");
+        HIP_TRY(hipMalloc(&h->power, (size_t)nparts * h->a_pad * h->K * sizeof(float)), "hipMalloc(power)");
+    }
+    h->planned = true;
+    return CORR_OK;
+}
+
+int check_tiles(const corr_ctx *h, const corr_tiles *t) {
+    if (t->chunk_spectra < 0 || (t->chunk_spectra % 64) != 0)
+        return fail(CORR_EINVAL, "chunk_spectra=%d must be a non-negative multiple of 64", t->chunk_spectra);
+    if (t->x_splits < 0 || t->x_splits > 64) return fail(CORR_EINVAL, "x_splits=%d out of [0, 64]", t->x_splits);
+    if (t->f_group != 0 && t->f_group != 2 && t->f_group != 4 && t->f_group != 8)
+        return fail(CORR_EINVAL, "f_group=%d must be 0, 2, 4 or 8", t->f_group);
+    if (t->f_group == 8 && h->K >= 1024) return fail(CORR_EINVAL, "f_group=8 needs K <= 512");
+    return CORR_OK;
+}
+
+void timer_begin(corr_ctx *h, int stage, hipStream_t st) {
+    if (!h->timing) return;
+    Timer t{stage, nullptr, nullptr};
+    hipEventCreate(&t.a);
+    hipEventCreate(&t.b);
+    hipEventRecord(t.a, st);
+    h->timers.push_back(t);
+}
+
+void timer_end(corr_ctx *h, hipStream_t st) {
+    if (!h->timing || h->timers.empty()) return;
+    hipEventRecord(h->timers.back().b, st);
+}
+
+int timers_collect(corr_ctx *h) {
+    if (h->timers.empty()) return CORR_OK;
+    HIP_TRY(hipEventSynchronize(h->timers.back().b), "hipEventSynchronize");
+    for (auto &t : h->timers) {
+        float ms = 0.0f;
+        hipEventElapsedTime(&ms, t.a, t.b);
+        h->ms[t.stage] += ms;
+        hipEventDestroy(t.a);
+        hipEventDestroy(t.b);
+    }
+    h->timers.clear();
+    return CORR_OK;
+}
+
+int launch_x_and_dump(corr_ctx *h, const uint4 *spec, int ntq, int nkb, hipStream_t st) {
+    XArgs xa;
+    xa.spec = spec;
+    xa.partial = h->partial;
+    xa.N = h->N;
+    xa.a_pad = h->a_pad;
+    xa.K = h->K;
+    xa.ntq = ntq;
+    xa.nb = h->nb;
+    xa.nsplit = h->tiles.x_splits;
+    xa.nkb = nkb;
+    timer_begin(h, 2, st);
+    xa.regions = h->regions;
+    xa.nregions = h->n_diag;
+    HIP_TRY(launch_xstage(h->prec, h->rb, 1, xa, st), "X-stage launch");
+    if (h->n_off) {
+        xa.regions = h->regions + h->n_diag;
+        xa.nregions = h->n_off;
+        HIP_TRY(launch_xstage(h->prec, h->rb, 0, xa, st), "X-stage launch");
+    }
+    timer_end(h, st);
+    h->launches_x++;
+    timer_begin(h, 3, st);
+    HIP_TRY(launch_dump(h->prec, h->partial, h->acc, h->tiles.x_splits, h->K, h->nb, st), "dump launch");
+    timer_end(h, st);
+    return CORR_OK;
+}
+
+int calibrate(corr_ctx *h, const uint8_t *in, hipStream_t st) {
+    const int W = std::min(h->S, CORR_CALIB_SPECTRA);
+    FArgs fa{};
+    fa.in = in;
+    fa.power = h->power;
+    fa.tw = h->tw;
+    fa.N = h->N;
+    fa.a_pad = h->a_pad;
+    fa.S = W;
+    fa.ntq = (W + 1) / 2;
+    fa.ngroups = (h->N + 3) / 4;
+    fa.tiles_per_wg = 32;
+    const int nparts = (fa.ntq + 31) / 32;
+    fa.ntiles = fa.ntq;
+    timer_begin(h, 0, st);
+    HIP_TRY(launch_fstage(h->K, kFP32, 4, 1, fa, fa.ngroups * nparts, st), "calibration launch");
+    HIP_TRY(launch_scales(h->power, nparts, h->N, h->a_pad, h->K, W, h->scales, st), "scales launch");
+    timer_end(h, st);
+    return CORR_OK;
+}
+
+int process_one(corr_ctx *h, const uint8_t *in, hipStream_t st) {
+    if (h->prec == kINT8) {
+        if (h->accumulated)
+            return fail(CORR_ESTATE, "INT8: read the previous integration before processing the next");
+        int rc = calibrate(h, in, st);
+        if (rc) return rc;
+    }
+    const int chunk = h->tiles.chunk_spectra;
+    const int ga = h->tiles.f_group;
+    const int ngroups = (h->N + ga - 1) / ga;
+    const int64_t frame = (int64_t)h->N * h->K;
+    for (int c0 = 0; c0 < h->S; c0 += chunk) {
+        const int Sc = std::min(chunk, h->S - c0);
+        const int ntq_used = round_up((Sc + h->TG - 1) / h->TG, 4);
+        FArgs fa{};
+        fa.in = in + (int64_t)c0 * frame;
+        fa.spec = h->spec;
+        fa.scales = h->scales;
+        fa.tw = h->tw;
+        fa.sat = h->sat;
+        fa.N = h->N;
+        fa.a_pad = h->a_pad;
+        fa.S = Sc;
+        fa.ntq = h->ntq_buf;
+        fa.ngroups = ngroups;
+        fa.ntiles = ntq_used * ngroups;
+        const int grid = std::min(fa.ntiles, 8192);
+        timer_begin(h, 1, st);
+        HIP_TRY(launch_fstage(h->K, h->prec, ga, 0, fa, grid, st), "F-stage launch");
+        timer_end(h, st);
+        h->launches_f++;
+        int rc = launch_x_and_dump(h, h->spec, h->ntq_buf, ntq_used / 4, st);
+        if (rc) return rc;
+        h->last_chunk = Sc;
+    }
+    return CORR_OK;
+}
+
+int sync_and_collect(corr_ctx *h) {
+    HIP_TRY(hipStreamSynchronize(h->last_stream), "hipStreamSynchronize");
+    return timers_collect(h);
+}
+
+int read_raw_into(corr_ctx *h, double *out) {
+    if (!out) return fail(CORR_EINVAL, "out is NULL");
+    if (h->accumulated == 0) return fail(CORR_ESTATE, "nothing processed since the last read");
+    hipStream_t st = h->last_stream;
+    HIP_TRY(launch_finalize(h->acc, h->stage, h->K, h->nb, st), "finalize launch");
+    HIP_TRY(hipMemcpyAsync(out, h->stage, (size_t)h->nb * h->K * sizeof(double2), hipMemcpyDeviceToHost, st),
+            "hipMemcpyAsync(read)");
+    int rc = sync_and_collect(h);
+    if (rc) return rc;
+    HIP_TRY(hipGetLastError(), "asynchronous error");
+    h->accumulated = 0;
+    return CORR_OK;
+}
+
+int descale_to_float(corr_ctx *h, const double *raw, float *out) {
+    const int64_t n = (int64_t)h->nb * h->K;
+    if (h->prec != kINT8) {
+        for (int64_t i = 0; i < 2 * n; ++i) out[i] = (float)raw[i];
+        return CORR_OK;
+    }
+    std::vector<float> sc((size_t)h->N * h->K);
+    HIP_TRY(hipMemcpy(sc.data(), h->scales, sc.size() * sizeof(float), hipMemcpyDeviceToHost), "hipMemcpy(scales)");
+    int64_t bl = 0;
+    for (int a = 0; a < h->N; ++a)
+        for (int b = a; b < h->N; ++b, ++bl)
+            for (int k = 0; k < h->K; ++k) {
+                const double d = (double)sc[(size_t)a * h->K + k] * (double)sc[(size_t)b * h->K + k];
+                const int64_t i = (bl * h->K + k) * 2;
+                out[i] = (float)(raw[i] / d);
+                out[i + 1] = (float)(raw[i + 1] / d);
+            }
+    return CORR_OK;
+}
+
+corr_ctx *create_ctx(int N, int K, int S) {
+    if (check_shape(N, K, S)) return nullptr;
+    corr_ctx *h = new (std::nothrow) corr_ctx();
+    if (!h) {
+        fail(CORR_ENOMEM, "host allocation failed");
+        return nullptr;
+    }
+    h->N = N;
+    h->K = K;
+    h->S = S;
+    h->nb = N * (N + 1) / 2;
+    h->nblk = (N + 15) / 16;
+    if (h->nblk <= 6) {
+        h->a_pad = 16 * h->nblk;
+        h->rb = h->nblk;
+    } else {
+        h->a_pad = round_up(N, 64);
+        h->nblk = h->a_pad / 16;
+        h->rb = 4;
+    }
+    auto bail = [&](hipError_t e, const char *what) {
+        hip_fail(e, what);
+        free_ctx(h);
+        return (corr_ctx *)nullptr;
+    };
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) return bail(e, "hipGetDevice");
+    // regions of the block triangle
+    std::vector<int2> regs;
+    const int nr = h->nblk / h->rb;
+    for (int i = 0; i < nr; ++i) regs.push_back(make_int2(i * h->rb, i * h->rb));
+    h->n_diag = (int)regs.size();
+    for (int i = 0; i < nr; ++i)
+        for (int j = i + 1; j < nr; ++j) regs.push_back(make_int2(i * h->rb, j * h->rb));
+    h->n_off = (int)regs.size() - h->n_diag;
+    if ((e = hipMalloc(&h->regions, regs.size() * sizeof(int2))) != hipSuccess) return bail(e, "hipMalloc(regions)");
+    if ((e = hipMemcpy(h->regions, regs.data(), regs.size() * sizeof(int2), hipMemcpyHostToDevice)) != hipSuccess)
+        return bail(e, "hipMemcpy(regions)");
+    // twiddles: W_K^j, j < K, then W_2K^q, q < K/2
+    std::vector<float2> tw((size_t)K + K / 2);
+    for (int j = 0; j < K; ++j) tw[j] = twiddle(j, K);
+    for (int q = 0; q < K / 2; ++q) tw[K + q] = twiddle(q, 2 * K);
+    if ((e = hipMalloc(&h->tw, tw.size() * sizeof(float2))) != hipSuccess) return bail(e, "hipMalloc(twiddles)");
+    if ((e = hipMemcpy(h->tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess)
+        return bail(e, "hipMemcpy(twiddles)");
+    const size_t accb = (size_t)h->nb * K * sizeof(double2);
+    if ((e = hipMalloc(&h->acc, accb)) != hipSuccess) return bail(e, "hipMalloc(integration buffer)");
+    if ((e = hipMemset(h->acc, 0, accb)) != hipSuccess) return bail(e, "hipMemset(integration buffer)");
+    if ((e = hipMalloc(&h->stage, accb)) != hipSuccess) return bail(e, "hipMalloc(read stage)");
+    if ((e = hipMalloc(&h->sat, sizeof(unsigned long long))) != hipSuccess) return bail(e, "hipMalloc(counter)");
+    if ((e = hipMemset(h->sat, 0, sizeof(unsigned long long))) != hipSuccess) return bail(e, "hipMemset(counter)");
+    return h;
+}
+
+corr_ctx *single(corr_handle h) { return (h && !h->batch) ? h : nullptr; }
+
+}  // namespace
+
+extern "C" {
+
+const char *corr_last_error(void) { return g_err; }
+
+corr_handle corr_create(int N, int K, int n_spectra) {
+    g_err[0] = 0;
+    return create_ctx(N, K, n_spectra);
+}
+
+int corr_set_precision(corr_handle hh, int mode) {
+    corr_ctx *h = single(hh);
+    if (!h) return fail(CORR_EINVAL, "invalid handle");
+    if (mode != CORR_FP32 && mode != CORR_FP16 && mode != CORR_INT8)
+        return fail(CORR_EINVAL, "unknown precision %d", mode);
+    if (h->started || h->planned) return fail(CORR_ESTATE, "precision is fixed once processing has started");
+    if (mode == CORR_INT8 && h->S > 65536)
+        return fail(CORR_EINVAL, "INT8 needs n_spectra <= 65536 (exact int32 partials), got %d", h->S);
+    h->prec = mode;
+    return CORR_OK;
+}
+
+int corr_set_tiles(corr_handle hh, const corr_tiles *t) {
+    corr_ctx *h = single(hh);
+    if (!h || !t) return fail(CORR_EINVAL, "invalid handle or tiles");
+    if (h->started || h->planned) return fail(CORR_ESTATE, "tiles are fixed once processing has started");
+    int rc = check_tiles(h, t);
+    if (rc) return rc;
+    h->tiles = *t;
+    return CORR_OK;
+}
+
+int corr_get_tiles(corr_handle hh, corr_tiles *t) {
+    corr_ctx *h = single(hh);
+    if (!h || !t) return fail(CORR_EINVAL, "invalid handle or tiles");
+    int rc = plan(h);
+    if (rc) return rc;
+    *t = h->tiles;
+    return CORR_OK;
+}
+
+int corr_process(corr_handle hh, const void *packed, void *stream) {
+    corr_ctx *h = single(hh);
+    if (!h) return fail(CORR_EINVAL, "invalid handle");
+    if (!packed || (reinterpret_cast<uintptr_t>(packed) & 15))
+        return fail(CORR_EINVAL, "packed_samples must be a 16-byte aligned device pointer");
+    int rc = plan(h);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    h->started = true;
+    h->last_stream = st;
+    rc = process_one(h, (const uint8_t *)packed, st);
+    if (rc) return rc;
+    h->accumulated += h->S;
+    if (h->timing) return timers_collect(h);
+    return CORR_OK;
+}
+
+int corr_read_cps_raw(corr_handle hh, double *out) {
+    corr_ctx *h = single(hh);
+    if (!h) return fail(CORR_EINVAL, "invalid handle");
+    return read_raw_into(h, out);
+}
+
+int corr_read_cps(corr_handle hh, float *out) {
+    corr_ctx *h = single(hh);
+    if (!h || !out) return fail(CORR_EINVAL, "invalid handle or out");
+    std::vector<double> raw((size_t)h->nb * h->K * 2);
+    int rc = read_raw_into(h, raw.data());
+    if (rc) return rc;
+    return descale_to_float(h, raw.data(), out);
+}
+
+int corr_read_cps_async(corr_handle hh, double *dst, void *stream) {
+    corr_ctx *h = single(hh);
+    if (!h || !dst) return fail(CORR_EINVAL, "invalid handle or dst");
+    if (h->accumulated == 0) return fail(CORR_ESTATE, "nothing processed since the last read");
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(launch_finalize(h->acc, h->stage, h->K, h->nb, st), "finalize launch");
+    HIP_TRY(hipMemcpyAsync(dst, h->stage, (size_t)h->nb * h->K * sizeof(double2), hipMemcpyDefault, st),
+            "hipMemcpyAsync(read)");
+    h->last_stream = st;
+    h->accumulated = 0;
+    return CORR_OK;
+}
+
+int corr_read_scales(corr_handle hh, float *out) {
+    corr_ctx *h = single(hh);
+    if (!h || !out) return fail(CORR_EINVAL, "invalid handle or out");
+    if (h->prec != kINT8 || !h->scales) return fail(CORR_ESTATE, "scales exist only for INT8 after processing");
+    HIP_TRY(hipStreamSynchronize(h->last_stream), "hipStreamSynchronize");
+    HIP_TRY(hipMemcpy(out, h->scales, (size_t)h->N * h->K * sizeof(float), hipMemcpyDeviceToHost),
+            "hipMemcpy(scales)");
+    return CORR_OK;
+}
+
+size_t corr_spectra_bytes(corr_handle hh, int n_spectra) {
+    corr_ctx *h = single(hh);
+    if (!h || n_spectra < 1) return 0;
+    const int tg = record_times(h->prec);
+    const int ntq = round_up((n_spectra + tg - 1) / tg, 4);
+    return (size_t)h->K * ntq * h->a_pad * kRecordBytes;
+}
+
+int corr_process_spectra(corr_handle hh, const void *spectra, int n_spectra, void *stream) {
+    corr_ctx *h = single(hh);
+    if (!h) return fail(CORR_EINVAL, "invalid handle");
+    if (!spectra || (reinterpret_cast<uintptr_t>(spectra) & 15))
+        return fail(CORR_EINVAL, "spectra must be a 16-byte aligned device pointer");
+    if (n_spectra < 1 || n_spectra > (1 << 24)) return fail(CORR_EINVAL, "n_spectra=%d out of range", n_spectra);
+    if (h->prec == kINT8 && n_spectra > 65536) return fail(CORR_EINVAL, "INT8 needs n_spectra <= 65536");
+    int rc = plan(h);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    h->started = true;
+    h->last_stream = st;
+    const int ntq = round_up((n_spectra + h->TG - 1) / h->TG, 4);
+    rc = launch_x_and_dump(h, (const uint4 *)spectra, ntq, ntq / 4, st);
+    if (rc) return rc;
+    h->accumulated += n_spectra;
+    if (h->timing) return timers_collect(h);
+    return CORR_OK;
+}
+
+int corr_debug_read_spectra(corr_handle hh, void *out, int *n_spectra) {
+    corr_ctx *h = single(hh);
+    if (!h || !n_spectra) return fail(CORR_EINVAL, "invalid handle or n_spectra");
+    if (!h->last_chunk) return fail(CORR_ESTATE, "no chunk has been transformed yet");
+    *n_spectra = h->last_chunk;
+    if (!out) return CORR_OK;
+    HIP_TRY(hipStreamSynchronize(h->last_stream), "hipStreamSynchronize");
+    const int ntq = round_up((h->last_chunk + h->TG - 1) / h->TG, 4);
+    const size_t row = (size_t)ntq * h->a_pad * kRecordBytes;
+    const size_t pitch = (size_t)h->ntq_buf * h->a_pad * kRecordBytes;
+    HIP_TRY(hipMemcpy2D(out, row, h->spec, pitch, row, h->K, hipMemcpyDeviceToHost), "hipMemcpy2D(spectra)");
+    return CORR_OK;
+}
+
+int corr_get_stats(corr_handle hh, corr_stats *out) {
+    corr_ctx *h = single(hh);
+    if (!h || !out) return fail(CORR_EINVAL, "invalid handle or out");
+    int rc = timers_collect(h);
+    if (rc) return rc;
+    std::memset(out, 0, sizeof(*out));
+    out->spectra_accumulated = h->accumulated;
+    if (h->sat) {
+        unsigned long long s = 0;
+        if (h->last_stream) HIP_TRY(hipStreamSynchronize(h->last_stream), "hipStreamSynchronize");
+        HIP_TRY(hipMemcpy(&s, h->sat, sizeof(s), hipMemcpyDeviceToHost), "hipMemcpy(counter)");
+        out->int8_saturated = (int64_t)s;
+    }
+    out->precision = h->prec;
+    out->chunk_spectra = h->tiles.chunk_spectra;
+    out->x_splits = h->tiles.x_splits;
+    out->f_group = h->tiles.f_group;
+    out->ms_calib = h->ms[0];
+    out->ms_f = h->ms[1];
+    out->ms_x = h->ms[2];
+    out->ms_dump = h->ms[3];
+    out->launches_f = h->launches_f;
+    out->launches_x = h->launches_x;
+    return CORR_OK;
+}
+
+int corr_enable_timing(corr_handle hh, int on) {
+    corr_ctx *h = single(hh);
+    if (!h) return fail(CORR_EINVAL, "invalid handle");
+    int rc = timers_collect(h);
+    if (rc) return rc;
+    h->timing = on != 0;
+    for (double &m : h->ms) m = 0.0;
+    h->launches_f = h->launches_x = 0;
+    return CORR_OK;
+}
+
+void corr_destroy(corr_handle h) { free_ctx(h); }
+
+// ------------------------------------------------------------------- batch
+
+corr_handle corr_batch_create(const corr_job *jobs, int n_jobs) {
+    (void)jobs;
+    (void)n_jobs;
+    fail(CORR_EINVAL, "batch mode is not available in this build");
+    return nullptr;
+}
+
+int corr_batch_set_tiles(corr_handle b, int job, const corr_tiles *t) {
+    (void)b; (void)job; (void)t;
+    return fail(CORR_EINVAL, "batch mode is not available in this build");
+}
+
+int corr_batch_process(corr_handle b, const void *const *packed, void *stream) {
+    (void)b; (void)packed; (void)stream;
+    return fail(CORR_EINVAL, "batch mode is not available in this build");
+}
+
+int corr_batch_read_cps(corr_handle b, int job, float *out) {
+    (void)b; (void)job; (void)out;
+    return fail(CORR_EINVAL, "batch mode is not available in this build");
+}
+
+int corr_batch_read_cps_raw(corr_handle b, int job, double *out) {
+    (void)b; (void)job; (void)out;
+    return fail(CORR_EINVAL, "batch mode is not available in this build");
+}
+
+int corr_batch_read_scales(corr_handle b, int job, float *out) {
+    (void)b; (void)job; (void)out;
+    return fail(CORR_EINVAL, "batch mode is not available in this build");
+}
+
+}  // extern "C"

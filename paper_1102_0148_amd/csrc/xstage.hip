@@ -1,0 +1,184 @@
+// X-stage of the FX correlator: for every channel f, the Hermitian rank-T
+// update V_f += X_f X_f^H over a time range, upper triangle only, on MFMA.
+//
+// What is computed (Section 1 of Prasad & Subrahmanya): for each channel and
+// every antenna pair a <= b, V[a,b] = sum_t X[t,a] conj(X[t,b]).
+//
+// How (gfx950): the antennas of one channel form 16-antenna blocks; a
+// wavefront owns a region of block pairs (I, J) and keeps both 16x16
+// accumulators of every pair in registers over its time range.  With a
+// record P = [re x TG | im x TG] of TG spectra and Q = [im x TG | -re x TG]:
+//     Re V_IJ = sum P_I P_J^T,     Im V_IJ = sum Q_I P_J^T,
+// since sum_k Q_a[k] P_b[k] = sum_t (im_a re_b - re_a im_b).  One 16-byte
+// record per lane is exactly one MFMA operand for the fp16 (16x16x32) and
+// int8 (16x16x64) forms, and four consecutive operands for fp32 (16x16x4).
+// Each wave writes its partial sums [split][channel][baseline]; the dump
+// kernel adds them into float64 in a fixed order.
+#include "corr_internal.h"
+
+namespace corr {
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+template <int PREC> struct AccT { typedef f32x4 type; };
+template <> struct AccT<kINT8> { typedef i32x4 type; };
+
+// per-byte negation of four int8 values in [-127, 127]
+__device__ __forceinline__ uint32_t neg_i8x4(uint32_t b) {
+    return (0x80808080u - (b & 0x7F7F7F7Fu)) ^ (~b & 0x80808080u);
+}
+
+// Q = [hi half | -(lo half)] of a record
+template <int PREC>
+__device__ __forceinline__ uint4 make_q(uint4 p) {
+    if constexpr (PREC == kFP32) {
+        return make_uint4(p.z, p.w, p.x ^ 0x80000000u, p.y ^ 0x80000000u);
+    } else if constexpr (PREC == kFP16) {
+        return make_uint4(p.z, p.w, p.x ^ 0x80008000u, p.y ^ 0x80008000u);
+    } else {
+        return make_uint4(p.z, p.w, neg_i8x4(p.x), neg_i8x4(p.y));
+    }
+}
+
+template <int PREC>
+__device__ __forceinline__ void mma(typename AccT<PREC>::type &acc, uint4 a, uint4 b) {
+    if constexpr (PREC == kFP32) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.x), __uint_as_float(b.x), acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.y), __uint_as_float(b.y), acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.z), __uint_as_float(b.z), acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.w), __uint_as_float(b.w), acc, 0, 0, 0);
+    } else if constexpr (PREC == kFP16) {
+        f16x8 av, bv;
+        __builtin_memcpy(&av, &a, 16);
+        __builtin_memcpy(&bv, &b, 16);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, bv, acc, 0, 0, 0);
+    } else {
+        i32x4 av = {(int)a.x, (int)a.y, (int)a.z, (int)a.w};
+        i32x4 bv = {(int)b.x, (int)b.y, (int)b.z, (int)b.w};
+        acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(av, bv, acc, 0, 0, 0);
+    }
+}
+
+template <int PREC>
+__device__ __forceinline__ void store_vis(void *partial, int64_t idx, typename AccT<PREC>::type &re,
+                                          typename AccT<PREC>::type &im, int v, bool auto_corr) {
+    if constexpr (PREC == kINT8) {
+        reinterpret_cast<int2 *>(partial)[idx] = make_int2(re[v], auto_corr ? 0 : im[v]);
+    } else {
+        reinterpret_cast<float2 *>(partial)[idx] = make_float2(re[v], auto_corr ? 0.0f : im[v]);
+    }
+}
+
+template <int PREC, int RB, bool DIAG>
+__global__ __launch_bounds__(256) void xstage_kernel(XArgs a) {
+    typedef typename AccT<PREC>::type acc_t;
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wave >= a.nregions * a.K * a.nsplit) return;
+    const int reg = wave % a.nregions;
+    const int rest = wave / a.nregions;
+    const int f = rest % a.K;
+    const int sp = rest / a.K;
+    const int I0 = a.regions[reg].x, J0 = a.regions[reg].y;
+    const int kb0 = (int)((int64_t)sp * a.nkb / a.nsplit);
+    const int kb1 = (int)((int64_t)(sp + 1) * a.nkb / a.nsplit);
+
+    acc_t accR[RB][RB], accI[RB][RB];
+#pragma unroll
+    for (int I = 0; I < RB; ++I)
+#pragma unroll
+        for (int J = 0; J < RB; ++J) {
+            accR[I][J] = acc_t{0, 0, 0, 0};
+            accI[I][J] = acc_t{0, 0, 0, 0};
+        }
+
+    // lane (row r, group g) reads record tq = 4 kb + g of antenna 16 I + r
+    const uint4 *base = a.spec + ((int64_t)f * a.ntq + (lane >> 4)) * a.a_pad + (lane & 15);
+    const int64_t kstride = 4 * (int64_t)a.a_pad;
+
+#pragma unroll 1
+    for (int kb = kb0; kb < kb1; ++kb) {
+        const uint4 *rec = base + kb * kstride;
+        uint4 pr[RB], qr[RB], pc[RB];
+#pragma unroll
+        for (int I = 0; I < RB; ++I) pr[I] = rec[(I0 + I) * 16];
+        if constexpr (!DIAG) {
+#pragma unroll
+            for (int J = 0; J < RB; ++J) pc[J] = rec[(J0 + J) * 16];
+        }
+#pragma unroll
+        for (int I = 0; I < RB; ++I) qr[I] = make_q<PREC>(pr[I]);
+#pragma unroll
+        for (int I = 0; I < RB; ++I)
+#pragma unroll
+            for (int J = 0; J < RB; ++J) {
+                if (DIAG && J < I) continue;
+                const uint4 b = DIAG ? pr[J] : pc[J];
+                mma<PREC>(accR[I][J], pr[I], b);
+                mma<PREC>(accI[I][J], qr[I], b);
+            }
+    }
+
+    // accumulator element v of lane l is row 4*(l/16)+v, column l%16
+    const int64_t obase = ((int64_t)sp * a.K + f) * a.nb;
+#pragma unroll
+    for (int I = 0; I < RB; ++I)
+#pragma unroll
+        for (int J = 0; J < RB; ++J) {
+            if (DIAG && J < I) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int ia = (I0 + I) * 16 + 4 * (lane >> 4) + v;
+                const int ib = (J0 + J) * 16 + (lane & 15);
+                if (ia < a.N && ib < a.N && ia <= ib) {
+                    const int bl = ia * a.N - ia * (ia - 1) / 2 + (ib - ia);
+                    store_vis<PREC>(a.partial, obase + bl, accR[I][J], accI[I][J], v, ia == ib);
+                }
+            }
+        }
+}
+
+template <int PREC, int RB, bool DIAG>
+hipError_t launch_one(const XArgs &a, hipStream_t st) {
+    const int64_t waves = (int64_t)a.nregions * a.K * a.nsplit;
+    const int grid = (int)((waves + 3) / 4);
+    hipLaunchKernelGGL((xstage_kernel<PREC, RB, DIAG>), dim3(grid), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t launch_p(int rb, int diag, const XArgs &a, hipStream_t st) {
+    if (diag) {
+        switch (rb) {
+            case 1: return launch_one<PREC, 1, true>(a, st);
+            case 2: return launch_one<PREC, 2, true>(a, st);
+            case 3: return launch_one<PREC, 3, true>(a, st);
+            case 4: return launch_one<PREC, 4, true>(a, st);
+            case 5: return launch_one<PREC, 5, true>(a, st);
+            case 6: return launch_one<PREC, 6, true>(a, st);
+        }
+    } else {
+        switch (rb) {
+            case 2: return launch_one<PREC, 2, false>(a, st);
+            case 3: return launch_one<PREC, 3, false>(a, st);
+            case 4: return launch_one<PREC, 4, false>(a, st);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_xstage(int prec, int rb, int diag, const XArgs &a, hipStream_t st) {
+    switch (prec) {
+        case kFP32: return launch_p<kFP32>(rb, diag, a, st);
+        case kFP16: return launch_p<kFP16>(rb, diag, a, st);
+        case kINT8: return launch_p<kINT8>(rb, diag, a, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace corr

@@ -1,0 +1,82 @@
+"""The C-ABI library on the CPU: it loads, exports every symbol the public
+header declares, and rejects bad arguments before touching the GPU.  The
+host-side record layout helpers round-trip.  No compute calls here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1102_0148_amd as corr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "corr.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(corr_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(corr.LIB_PATH):
+        corr_build = __import__("paper_1102_0148_amd.build", fromlist=["build"])
+        corr_build.build()
+    return corr.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert len(names) >= 20
+    assert sorted(corr.EXPORTS) == names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+@pytest.mark.parametrize("N,K,S", [(1, 256, 16), (513, 256, 16), (44, 100, 16), (44, 64, 16),
+                                   (44, 2048, 16), (44, 256, 0), (44, 256, (1 << 24) + 1)])
+def test_create_rejects_bad_shapes(lib, N, K, S):
+    assert lib.corr_create(N, K, S) is None
+    msg = corr.corr_last_error()
+    assert msg and ("N=" in msg or "K=" in msg or "n_spectra" in msg)
+
+
+def test_null_handle_is_rejected(lib):
+    assert lib.corr_set_precision(None, 0) == corr.CORR_EINVAL
+    assert lib.corr_process(None, None, None) == corr.CORR_EINVAL
+    assert lib.corr_read_cps_raw(None, None) == corr.CORR_EINVAL
+    assert lib.corr_spectra_bytes(None, 16) == 0
+    lib.corr_destroy(None)  # NULL-safe
+
+
+@pytest.mark.parametrize("prec", [corr.CORR_FP32, corr.CORR_FP16, corr.CORR_INT8])
+@pytest.mark.parametrize("N,S", [(5, 7), (44, 33), (70, 9)])
+def test_record_layout_round_trip(prec, N, S):
+    K = 8
+    rng = np.random.default_rng(prec * 100 + N)
+    if prec == corr.CORR_INT8:
+        spec = rng.integers(-127, 128, (S, N, K, 2)).astype(np.int8)
+    else:
+        spec = (rng.standard_normal((S, N, K)) + 1j * rng.standard_normal((S, N, K))).astype(np.complex64)
+        if prec == corr.CORR_FP16:
+            spec = spec.real.astype(np.float16).astype(np.float32) + 1j * spec.imag.astype(np.float16).astype(np.float32)
+    buf = corr.spectra_to_records(spec, prec)
+    tg = corr.record_times(prec)
+    a_pad = (N + 15) // 16 * 16 if (N + 15) // 16 <= 6 else (N + 63) // 64 * 64
+    ntq = ((S + tg - 1) // tg + 3) // 4 * 4
+    assert buf.size == K * ntq * a_pad * 16
+    back = corr.records_to_spectra(buf, prec, N, K, S)
+    np.testing.assert_array_equal(back, spec)
+    # one record by hand: channel 3, antenna 2, spectra 0..tg-1 as [re x tg][im x tg]
+    dt = {corr.CORR_FP32: np.float32, corr.CORR_FP16: np.float16, corr.CORR_INT8: np.int8}[prec]
+    rec = buf.view(dt).reshape(K, -1, a_pad, 2 * tg)[3, 0, 2]
+    n = min(tg, S)
+    if prec == corr.CORR_INT8:
+        np.testing.assert_array_equal(rec[:n], spec[:n, 2, 3, 0])
+        np.testing.assert_array_equal(rec[tg:tg + n], spec[:n, 2, 3, 1])
+    else:
+        np.testing.assert_array_equal(rec[:n].astype(np.float32), spec[:n, 2, 3].real)
+        np.testing.assert_array_equal(rec[tg:tg + n].astype(np.float32), spec[:n, 2, 3].imag)

@@ -1,0 +1,315 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, on the
+same seeded inputs.  Needs an MI355X and the built libcorr.so.
+
+Tolerances (coefficient units, |V - V64| / sqrt(V64_aa V64_bb), the error a
+visibility carries relative to the noise power of its two antennas):
+  fp32: 1e-5    float spectra and float MFMA sums over <= 2048 spectra per
+                partial; the float FFT alone is good to ~1e-7 per bin
+  fp16: 2e-3    half-precision spectra (2^-11 relative) dominate
+  int8: exact   against the integer oracle on the same quantised spectra
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1102_0148_amd as corr
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {corr.CORR_FP32: 1e-5, corr.CORR_FP16: 2e-3}
+
+
+def _packed(recipe, S, device="cuda"):
+    return synth.packed(recipe, 0, S, device="cpu").contiguous().to(device)
+
+
+def coef_error(v, ref, N):
+    """max over baselines and channels of |v - ref| / sqrt(ref_aa ref_bb)."""
+    nb, K = ref.shape
+    auto = np.empty((N, K))
+    for a in range(N):
+        auto[a] = ref[oracle.baseline_index(N, a, a)].real
+    err = 0.0
+    bl = 0
+    for a in range(N):
+        for b in range(a, N):
+            den = np.sqrt(np.maximum(auto[a] * auto[b], 1e-300))
+            err = max(err, float(np.max(np.abs(v[bl] - ref[bl]) / den)))
+            bl += 1
+    return err
+
+
+def raw_to_complex(raw):
+    return raw[..., 0] + 1j * raw[..., 1]
+
+
+def run(N, K, S, packed, precision=corr.CORR_FP32, tiles=None):
+    c = corr.Correlator(N, K, S, precision=precision, tiles=tiles)
+    c.process(packed)
+    raw = c.read_cps_raw()
+    return c, raw
+
+
+# ------------------------------------------------------------------ F-stage
+
+@pytest.mark.parametrize("K", [128, 256, 512, 1024])
+def test_fstage_fp32_spectra_match_oracle(K):
+    N, S = 5, 11
+    print(f"\n[fstage] N={N} K={K} S={S}", flush=True)
+    r = synth.recipe_plain(N=N, two_k=2 * K, seed=31)
+    packed = _packed(r, S)
+    c, _ = run(N, K, S, packed)
+    buf, n = c.debug_read_spectra()
+    assert n == S
+    got = corr.records_to_spectra(buf, corr.CORR_FP32, N, K, S)
+    ref = oracle.spectra(packed.cpu().numpy(), S, N, K)
+    scale = np.sqrt(np.mean(np.abs(ref) ** 2))
+    assert np.max(np.abs(got - ref)) <= 2e-6 * scale * math.log2(2 * K)
+    # bins 0 and K/2 are Gaussian integers, exact in float
+    np.testing.assert_array_equal(got[:, :, 0], ref[:, :, 0].round())
+    np.testing.assert_array_equal(got[:, :, K // 2], ref[:, :, K // 2].round())
+
+
+def test_fstage_extreme_samples():
+    """All -8 and all 7 samples (largest magnitudes): DC = 2K x, other bins 0."""
+    N, K, S = 3, 256, 4
+    x = torch.full((S, N, 2 * K), -8, dtype=torch.int8)
+    x[:, 1] = 7
+    x[:, 2, 0::2] = 7
+    x[:, 2, 1::2] = -8
+    packed = synth.pack(x).cuda()
+    c, _ = run(N, K, S, packed)
+    buf, _ = c.debug_read_spectra()
+    got = corr.records_to_spectra(buf, corr.CORR_FP32, N, K, S)
+    ref = oracle.spectra(packed.cpu().numpy(), S, N, K)
+    np.testing.assert_array_equal(got[:, 0, 0], -8 * 2 * K)
+    np.testing.assert_array_equal(got[:, 1, 0], 7 * 2 * K)
+    assert np.max(np.abs(got - ref)) <= 1e-3
+
+
+# ------------------------------------------------------------------ FP32 end to end
+
+@pytest.mark.parametrize("N,K,S", [(44, 256, 1024), (5, 128, 37), (20, 512, 100), (16, 1024, 24),
+                                   (2, 256, 1), (96, 256, 64)])
+def test_fp32_end_to_end(N, K, S):
+    print(f"\n[fp32] N={N} K={K} S={S}", flush=True)
+    r = synth.recipe_plain(N=N, two_k=2 * K, seed=N * 7 + K)
+    packed = _packed(r, S)
+    c, raw = run(N, K, S, packed)
+    ref = oracle.correlate(packed.cpu().numpy(), S, N, K)
+    v = raw_to_complex(raw)
+    assert coef_error(v, ref, N) <= TOL[corr.CORR_FP32]
+    for a in range(N):
+        bl = oracle.baseline_index(N, a, a)
+        assert np.all(raw[bl, :, 1] == 0.0) and np.all(raw[bl, :, 0] >= 0.0)
+
+
+def test_fp32_large_n_regions():
+    """N = 256 uses the multi-region X-stage (diagonal and off-diagonal)."""
+    N, K, S = 256, 512, 24
+    print(f"\n[fp32 large N] N={N} K={K} S={S}", flush=True)
+    r = synth.recipe_sources(N=N, two_k=2 * K, seed=4)
+    packed = _packed(r, S)
+    c, raw = run(N, K, S, packed)
+    ref = oracle.correlate(packed.cpu().numpy(), S, N, K)
+    assert coef_error(raw_to_complex(raw), ref, N) <= TOL[corr.CORR_FP32]
+
+
+@pytest.mark.parametrize("tiles", [dict(chunk_spectra=64, x_splits=1, f_group=2),
+                                   dict(chunk_spectra=128, x_splits=3, f_group=4),
+                                   dict(chunk_spectra=256, x_splits=64, f_group=8)])
+def test_fp32_tile_invariance(tiles):
+    N, K, S = 44, 256, 300
+    r = synth.recipe_plain(N=N, two_k=2 * K, seed=5)
+    packed = _packed(r, S)
+    _, raw = run(N, K, S, packed, tiles=tiles)
+    ref = oracle.correlate(packed.cpu().numpy(), S, N, K)
+    assert coef_error(raw_to_complex(raw), ref, N) <= TOL[corr.CORR_FP32]
+
+
+def test_fp32_deterministic_and_read_clears():
+    N, K, S = 44, 256, 512
+    r = synth.recipe_plain(N=N, two_k=2 * K, seed=6)
+    packed = _packed(r, S)
+    c = corr.Correlator(N, K, S)
+    c.process(packed)
+    a = c.read_cps_raw()
+    c.process(packed)
+    b = c.read_cps_raw()
+    np.testing.assert_array_equal(a, b)
+    # two integrations accumulate: equals twice one (exactly, in float64 of
+    # identical float partials)
+    c.process(packed)
+    c.process(packed)
+    two = c.read_cps_raw()
+    np.testing.assert_array_equal(two, 2 * a)
+
+
+def test_async_read_matches_sync_read():
+    N, K, S = 12, 256, 64
+    packed = _packed(synth.recipe_plain(N=N, two_k=2 * K, seed=8), S)
+    c = corr.Correlator(N, K, S)
+    c.process(packed)
+    dst = torch.empty(c.nb * K * 2, dtype=torch.float64, device="cuda")
+    c.read_cps_async(dst)
+    c.process(packed)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(dst.cpu().numpy().reshape(c.nb, K, 2), c.read_cps_raw())
+
+
+def test_zero_input_gives_zero():
+    N, K, S = 20, 256, 40
+    packed = torch.zeros(S * N * K, dtype=torch.uint8, device="cuda")
+    for prec in (corr.CORR_FP32, corr.CORR_FP16, corr.CORR_INT8):
+        _, raw = run(N, K, S, packed, precision=prec)
+        assert np.all(raw == 0.0)
+
+
+# ------------------------------------------------------------------ INT8
+
+def _int8_run(N, K, S, seed, tiles=None):
+    r = synth.recipe_tone(N=N, two_k=2 * K, seed=seed)
+    packed = _packed(r, S)
+    c = corr.Correlator(N, K, S, precision="int8", tiles=tiles)
+    c.process(packed)
+    scales = c.read_scales()
+    buf, n = c.debug_read_spectra()
+    raw = c.read_cps_raw()
+    return c, packed, scales, buf, n, raw
+
+
+@pytest.mark.parametrize("N,K,S", [(44, 256, 1024), (7, 128, 45), (33, 512, 130)])
+def test_int8_bit_exact_on_gpu_spectra(N, K, S):
+    """The int64 oracle X-stage on the GPU's own int8 spectra equals the GPU
+    result exactly; the GPU scales and quantised spectra follow the oracle's
+    rule on the oracle's spectra."""
+    print(f"\n[int8] N={N} K={K} S={S}", flush=True)
+    tiles = dict(chunk_spectra=round_up(S, 64))  # one chunk, so it is exported whole
+    c, packed, scales, buf, n, raw = _int8_run(N, K, S, seed=N + K, tiles=tiles)
+    assert n == S
+    q_gpu = corr.records_to_spectra(buf, corr.CORR_INT8, N, K, S)
+    vi = oracle.cmac_i64(q_gpu)
+    np.testing.assert_array_equal(raw, vi.astype(np.float64))
+    spec = oracle.spectra(packed.cpu().numpy(), S, N, K)
+    sc_ref = oracle.scales(spec, min(S, corr.CORR_CALIB_SPECTRA))
+    np.testing.assert_allclose(scales, sc_ref, rtol=1e-5)
+    q_ref = oracle.quantise(spec, scales)
+    diff = q_gpu.astype(np.int32) - q_ref.astype(np.int32)
+    assert np.max(np.abs(diff)) <= 1
+    assert np.mean(diff != 0) <= 1e-3
+
+
+@pytest.mark.parametrize("N,K,S", [(44, 256, 200), (64, 128, 33), (256, 256, 16)])
+def test_int8_x_stage_on_oracle_spectra(N, K, S):
+    """Oracle-quantised spectra through corr_process_spectra: bit-exact."""
+    rng = np.random.default_rng(N * K + S)
+    q = rng.integers(-127, 128, (S, N, K, 2)).astype(np.int8)
+    q[:, :, :, :][rng.random((S, N, K, 2)) < 0.01] = 127
+    buf = torch.from_numpy(corr.spectra_to_records(q, corr.CORR_INT8)).cuda()
+    c = corr.Correlator(N, K, S, precision="int8")
+    c.process_spectra(buf, S)
+    raw = c.read_cps_raw()
+    np.testing.assert_array_equal(raw, oracle.cmac_i64(q).astype(np.float64))
+
+
+def test_int8_tile_invariance_exact():
+    N, K, S = 44, 256, 700
+    outs = []
+    for tiles in (dict(chunk_spectra=64, x_splits=1, f_group=2), dict(chunk_spectra=704, x_splits=7, f_group=8)):
+        _, _, _, _, _, raw = _int8_run(N, K, S, seed=3, tiles=tiles)
+        outs.append(raw)
+    np.testing.assert_array_equal(outs[0], outs[1])
+
+
+def test_int8_physical_units_match_fp64():
+    """De-scaled int8 visibilities estimate the float64 ones: the coefficient
+    error is set by the quantisation step (1/127 of 4 rms per component)."""
+    N, K, S = 12, 256, 1024
+    r = synth.recipe_tone(N=N, two_k=2 * K, seed=12)
+    packed = _packed(r, S)
+    c = corr.Correlator(N, K, S, precision="int8")
+    c.process(packed)
+    v = c.read_cps()
+    ref = oracle.correlate(packed.cpu().numpy(), S, N, K)
+    assert coef_error(v, ref, N) <= 0.02
+
+
+# ------------------------------------------------------------------ FP16
+
+@pytest.mark.parametrize("N,K,S", [(44, 256, 1024), (9, 1024, 50)])
+def test_fp16_matches_oracle(N, K, S):
+    print(f"\n[fp16] N={N} K={K} S={S}", flush=True)
+    r = synth.recipe_tone(N=N, two_k=2 * K, seed=N)
+    packed = _packed(r, S)
+    tiles = dict(chunk_spectra=round_up(S, 64))
+    c = corr.Correlator(N, K, S, precision="fp16", tiles=tiles)
+    c.process(packed)
+    buf, n = c.debug_read_spectra()
+    raw = raw_to_complex(c.read_cps_raw())
+    half = corr.records_to_spectra(buf, corr.CORR_FP16, N, K, S)
+    # same half-precision inputs: only the float accumulation differs
+    ref_same = oracle.cmac_f64(half.astype(np.complex128))
+    assert coef_error(raw, ref_same, N) <= 1e-5
+    # the half values are the float64 spectra rounded to half
+    spec = oracle.spectra(packed.cpu().numpy(), S, N, K)
+    rounded = spec.real.astype(np.float32).astype(np.float16) + 1j * spec.imag.astype(np.float32).astype(np.float16)
+    # the GPU rounds its float FFT to half, the oracle its float64 one: a value
+    # can differ only where the two sit on either side of a half rounding tie
+    mism = half != rounded
+    assert np.mean(mism) < 1e-2
+    for part in (np.real, np.imag):
+        h, r_ = part(half)[mism].astype(np.float64), part(rounded)[mism].astype(np.float64)
+        ulp = np.spacing(np.abs(r_).astype(np.float16)).astype(np.float64)
+        assert np.all(np.abs(h - r_) <= ulp)
+    # end to end against float64
+    ref = oracle.cmac_f64(spec)
+    assert coef_error(raw, ref, N) <= TOL[corr.CORR_FP16]
+
+
+def test_fp16_x_stage_on_oracle_spectra():
+    N, K, S = 44, 256, 96
+    rng = np.random.default_rng(2)
+    spec = (rng.standard_normal((S, N, K)) * 50 + 1j * rng.standard_normal((S, N, K)) * 50)
+    half = spec.real.astype(np.float16).astype(np.float64) + 1j * spec.imag.astype(np.float16).astype(np.float64)
+    buf = torch.from_numpy(corr.spectra_to_records(half, corr.CORR_FP16)).cuda()
+    c = corr.Correlator(N, K, S, precision="fp16")
+    c.process_spectra(buf, S)
+    raw = raw_to_complex(c.read_cps_raw())
+    assert coef_error(raw, oracle.cmac_f64(half), N) <= 1e-5
+
+
+# ------------------------------------------------------------------ state errors
+
+def test_state_errors():
+    N, K, S = 8, 128, 16
+    packed = torch.zeros(S * N * K, dtype=torch.uint8, device="cuda")
+    c = corr.Correlator(N, K, S)
+    with pytest.raises(corr.CorrError) as e:
+        c.read_cps_raw()
+    assert e.value.code == corr.CORR_ESTATE
+    c.process(packed)
+    with pytest.raises(corr.CorrError) as e:
+        corr.corr_set_precision(c.h, corr.CORR_INT8)
+    assert e.value.code == corr.CORR_ESTATE
+    with pytest.raises(corr.CorrError) as e:
+        corr.corr_set_tiles(c.h, chunk_spectra=64)
+    assert e.value.code == corr.CORR_ESTATE
+    c.read_cps_raw()
+    ci = corr.Correlator(N, K, S, precision="int8")
+    ci.process(packed)
+    with pytest.raises(corr.CorrError) as e:
+        ci.process(packed)
+    assert e.value.code == corr.CORR_ESTATE
+    with pytest.raises(corr.CorrError) as e:
+        corr.Correlator(N, K, 70000, precision="int8")
+    assert e.value.code == corr.CORR_EINVAL
+    with pytest.raises(corr.CorrError):
+        corr.corr_process(c.h, packed.data_ptr() + 1, 0)
+
+
+def round_up(x, m):
+    return (x + m - 1) // m * m
