@@ -1,0 +1,221 @@
+"""Throughput of the FX correlator hot path on one MI355X.
+
+Workload: N = 44 antennas, 512-point real FFT -> K = 256 channels, 4-bit
+samples (sigma = 2.5 Gaussian noise per antenna plus a common component at
+rho = 0.05), 65536 spectra per integration (~33.5 M samples per antenna, about
+1 s at the paper's ~35 MS/s), 4 consecutive integrations per step.  Inputs are
+generated on the GPU and resident in HBM before timing starts.  One step = the
+whole path (unpack, F-stage, corner turn, X-stage, float64 dump and the
+asynchronous read of each integration's result) over the 4 integrations.
+
+`value` is the float32 path's sustained rate in antenna-MS/s (antenna-samples
+per second / 1e6); the fp16 and int8 forms run the same step on the same input
+and are reported beside it with their X-stage TOPS, speedup over float32 and
+measured error against the float64 oracle (on a 1024-spectrum sample).
+
+`roofline` is for the dominant kernel of the float32 step, from HIP events the
+library records around each stage on the stream it launches on.
+`cpu_baseline` times the CPU oracle (float64 FFT + pairwise CMAC) on a bounded
+sample of the same workload on this host's cores.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N_ANT, TWO_K, S_INT, N_INT = 44, 512, 65536, 4
+K = TWO_K // 2
+PAPER_ANTENNA_MSPS = 1470.0     # 735 MB/s of 4-bit samples (abstract), 4-node Xeon system
+PEAK = {"hbm_gbs": 8000.0, "fp32_tflops": 157.3, "fp16_tflops": 2500.0, "int8_tops": 5000.0}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_inputs(device):
+    import synth
+    recipe = synth.recipe_plain(N=N_ANT, two_k=TWO_K, rho=0.05, seed=1)
+    bufs = []
+    for i in range(N_INT):
+        bufs.append(synth.packed(recipe, i * S_INT, (i + 1) * S_INT, device=device).contiguous())
+        log(f"[bench] generated integration {i + 1}/{N_INT}")
+    return bufs
+
+
+def run_form(corr, torch, precision, inputs, steps, warmup, timing=False):
+    c = corr.Correlator(N_ANT, K, S_INT, precision=precision)
+    dst = torch.empty(c.nb * K * 2, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        for x in inputs:
+            c.process(x, stream)
+            c.read_cps_async(dst, stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    if timing:
+        c.enable_timing(True)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t0.record(stream)
+    for _ in range(steps):
+        step()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = t0.elapsed_time(t1)
+    stats = c.stats()
+    tiles = c.tiles()
+    c.close()
+    return ms / steps, wall / steps * 1e3, stats, tiles
+
+
+def accuracy(corr, torch, precision):
+    """Coefficient error vs the float64 oracle on the first 1024 spectra."""
+    import numpy as np
+    import oracle
+    import synth
+    S = 1024
+    recipe = synth.recipe_plain(N=N_ANT, two_k=TWO_K, rho=0.05, seed=1)
+    packed = synth.packed(recipe, 0, S, device="cpu").contiguous()
+    c = corr.Correlator(N_ANT, K, S, precision=precision)
+    c.process(packed.cuda())
+    v = c.read_cps()
+    c.close()
+    ref = oracle.correlate(packed.numpy(), S, N_ANT, K)
+    auto = np.array([ref[oracle.baseline_index(N_ANT, a, a)].real for a in range(N_ANT)])
+    err, bl = 0.0, 0
+    for a in range(N_ANT):
+        for b in range(a, N_ANT):
+            err = max(err, float(np.max(np.abs(v[bl] - ref[bl]) / np.sqrt(auto[a] * auto[b]))))
+            bl += 1
+    return err
+
+
+def cpu_baseline(inputs_cpu_sample, S_sample):
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    oracle.correlate(inputs_cpu_sample, S_sample, N_ANT, K)
+    dt = time.perf_counter() - t0
+    rate = N_ANT * S_sample * TWO_K / dt / 1e6
+    return {"value": round(rate, 3), "unit": "antenna-MS/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {S_sample} spectra of integration 1 (N={N_ANT}, 2K={TWO_K}), "
+                      f"float64 FFT + pairwise CMAC, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-spectra", type=int, default=8192)
+    ap.add_argument("--forms", default="fp32,fp16,int8")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the time-domain sharding across GPUs is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1102_0148_amd as corr
+    from paper_1102_0148_amd import metrics
+
+    torch.cuda.set_device(0)
+    inputs = make_inputs("cuda")
+    torch.cuda.synchronize()
+
+    a_s_per_step = N_INT * metrics.antenna_samples(N_ANT, TWO_K, S_INT)
+    xops_per_int = metrics.x_ops(N_ANT, K, S_INT)
+    forms = {}
+    for name in args.forms.split(","):
+        ms, wall_ms, stats, tiles = run_form(corr, torch, name, inputs, args.steps, args.warmup, timing=True)
+        n_int = args.steps * N_INT
+        x_ms = stats["ms_x"] / n_int
+        f_ms = stats["ms_f"] / n_int
+        forms[name] = {
+            "antenna_msps": round(a_s_per_step / (ms * 1e-3) / 1e6, 1),
+            "ms_per_step": round(ms, 4),
+            "x_tops": round(xops_per_int / (x_ms * 1e-3) / 1e12, 2) if x_ms > 0 else None,
+            "ms_per_integration": {"f": round(f_ms, 4), "x": round(x_ms, 4),
+                                   "dump": round(stats["ms_dump"] / n_int, 4),
+                                   "calib": round(stats["ms_calib"] / n_int, 4)},
+            "launches_per_integration": {"f": stats["launches_f"] // n_int, "x": stats["launches_x"] // n_int},
+            "tiles": tiles,
+        }
+        if name == "int8":
+            forms[name]["int8_saturated_fraction"] = stats["int8_saturated"] / max(
+                1, (args.steps + args.warmup) * N_INT * S_INT * N_ANT * K * 2)
+        log(f"[bench] {name}: {forms[name]}")
+    for name in forms:
+        forms[name]["coef_error_vs_fp64"] = float("%.3g" % accuracy(corr, torch, name))
+        if "fp32" in forms:
+            forms[name]["speedup_vs_fp32"] = round(forms[name]["antenna_msps"] / forms["fp32"]["antenna_msps"], 3)
+
+    head = forms.get("fp32") or next(iter(forms.values()))
+    ms_step = head["ms_per_step"]
+    value = head["antenna_msps"]
+
+    # roofline of the dominant kernel of the headline step
+    st = head["ms_per_integration"]
+    launches = head["launches_per_integration"]
+    chunk = head["tiles"]["chunk_spectra"]
+    if st["x"] >= st["f"]:
+        per_launch_ms = st["x"] / max(1, launches["x"])
+        flops = metrics.x_ops(N_ANT, K, chunk)
+        achieved = flops / (per_launch_ms * 1e-3) / 1e12
+        roof = {"kernel": "xstage_kernel (fp32 MFMA, Hermitian rank-T update)", "bound": "mfma",
+                "achieved": round(achieved, 2), "peak": PEAK["fp32_tflops"], "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK["fp32_tflops"], 4), "traffic": None,
+                "per_launch": {"useful_flops": flops, "avg_ms": round(per_launch_ms, 4)}}
+    else:
+        per_launch_ms = st["f"] / max(1, launches["f"])
+        nbytes = metrics.antenna_samples(N_ANT, TWO_K, chunk) * (0.5 + 4.0)
+        achieved = nbytes / (per_launch_ms * 1e-3) / 1e9
+        roof = {"kernel": "fstage_kernel (unpack + FFT + corner turn, fp32 records)", "bound": "hbm",
+                "achieved": round(achieved, 1), "peak": PEAK["hbm_gbs"], "unit": "GB/s",
+                "frac": round(achieved / PEAK["hbm_gbs"], 4), "traffic": None,
+                "per_launch": {"algorithmic_bytes": nbytes, "avg_ms": round(per_launch_ms, 4)}}
+
+    out = {
+        "metric": "antenna-MS/s sustained (F+X) and X-stage TOPS: int8/FP16 vs FP32 path",
+        "value": value,
+        "unit": "antenna-MS/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": round(value / PAPER_ANTENNA_MSPS, 1),
+        "baseline_note": "paper: ~735 MB/s of 4-bit input = 1470 antenna-MS/s on 4 dual Xeon E5430 nodes",
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"FX correlator N={N_ANT} antennas, {TWO_K}-pt real FFT -> {K} channels, "
+                               f"{S_INT} spectra/integration x {N_INT} integrations, float32 path",
+                   "N": N_ANT, "fft_points": TWO_K, "channels": K, "spectra_per_integration": S_INT,
+                   "integrations_per_step": N_INT, "parallelism": "single GPU"},
+        "x_tops": head["x_tops"],
+        "forms": forms,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        import numpy as np
+        sample = inputs[0][:args.cpu_spectra].cpu().numpy()
+        out["cpu_baseline"] = cpu_baseline(sample, args.cpu_spectra)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

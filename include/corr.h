@@ -124,10 +124,12 @@ int corr_read_scales(corr_handle h, float *out);
 /* Bytes of spectra in the library layout for n_spectra spectra (the size of
  * the buffer corr_process_spectra reads and corr_debug_read_spectra writes),
  * or 0 on error.  Layout: records of 16 bytes indexed
- * [channel][tq][antenna_pad], tq = t / TG, antenna_pad = N rounded up to 16,
- * tq padded to a multiple of 4; a record holds TG consecutive spectra of one
- * antenna and channel as [re x TG][im x TG] in the precision's type (float,
- * TG=2; half, TG=4; int8, TG=8).  Padding records and antennas are zero.  */
+ * [tq / 16][channel][tq mod 16][antenna_pad], tq = t / TG, antenna_pad = N
+ * rounded up to 16 (to 64 above 96 antennas), tq padded to a multiple of 16;
+ * a record holds TG consecutive spectra of one antenna and channel as
+ * [re x TG][im x TG] in the precision's type (float, TG=2; half, TG=4; int8,
+ * TG=8).  Records of padding antennas, and of spectra from n_spectra up to
+ * the next multiple of 4*TG, must be zero.  */
 size_t corr_spectra_bytes(corr_handle h, int n_spectra);
 
 /* X-stage + dump only, on n_spectra spectra already in the library layout
@@ -141,7 +143,8 @@ int corr_process_spectra(corr_handle h, const void *spectra, int n_spectra, void
 int corr_debug_read_spectra(corr_handle h, void *out, int *n_spectra);
 
 /* Counters and, when timing is on, per-stage GPU time summed over the calls
- * since the last read (HIP events on the caller's stream).  */
+ * since timing was enabled (HIP events recorded on the caller's stream around
+ * each stage; they are read, which waits for them, only here).  */
 typedef struct {
     int64_t spectra_accumulated; /* spectra in the integration buffer */
     int64_t int8_saturated;      /* components clamped to +-127 (INT8) */

@@ -319,9 +319,17 @@ def record_times(precision: int) -> int:
     return {CORR_FP32: 2, CORR_FP16: 4, CORR_INT8: 8}[precision]
 
 
+TQB = 16  # records per time block
+
+
+def a_pad_of(N: int) -> int:
+    nblk = (N + 15) // 16
+    return 16 * nblk if nblk <= 6 else (N + 63) // 64 * 64
+
+
 def spectra_to_records(spec: np.ndarray, precision: int) -> np.ndarray:
     """Lay out spectra [S][N][K] (complex for fp32/fp16; int8 [S][N][K][2] for
-    int8) as the library's records [K][tq][a_pad][re x TG | im x TG] bytes."""
+    int8) as the library's records [tq/16][K][tq%16][a_pad][re x TG | im x TG]."""
     tg = record_times(precision)
     if precision == CORR_INT8:
         S, N, K, _ = spec.shape
@@ -331,13 +339,14 @@ def spectra_to_records(spec: np.ndarray, precision: int) -> np.ndarray:
         S, N, K = spec.shape
         re, im = spec.real, spec.imag
         dt = np.float32 if precision == CORR_FP32 else np.float16
-    a_pad = (N + 15) // 16 * 16 if (N + 15) // 16 <= 6 else (N + 63) // 64 * 64
-    ntq = ((S + tg - 1) // tg + 3) // 4 * 4
-    out = np.zeros((K, ntq, a_pad, 2, tg), dtype=dt)
-    t = np.arange(S)
-    # advanced indices (t // tg, 0, t % tg) put the time axis first: [S][K][N]
-    out[:, t // tg, :N, 0, t % tg] = np.transpose(re, (0, 2, 1)).astype(dt)
-    out[:, t // tg, :N, 1, t % tg] = np.transpose(im, (0, 2, 1)).astype(dt)
+    a_pad = a_pad_of(N)
+    ntq = ((S + tg - 1) // tg + TQB - 1) // TQB * TQB
+    out = np.zeros((ntq // TQB, K, TQB, a_pad, 2, tg), dtype=dt)
+    tq = np.arange(S) // tg
+    tb, tr, tt = tq // TQB, tq % TQB, np.arange(S) % tg
+    # advanced indices (tb, tr, 0, tt) around the channel slice: [S][K][N]
+    out[tb, :, tr, :N, 0, tt] = np.transpose(re, (0, 2, 1)).astype(dt)
+    out[tb, :, tr, :N, 1, tt] = np.transpose(im, (0, 2, 1)).astype(dt)
     return out.view(np.uint8).reshape(-1)
 
 
@@ -346,12 +355,13 @@ def records_to_spectra(buf: np.ndarray, precision: int, N: int, K: int, S: int) 
     or int8 [S][N][K][2] (int8)."""
     tg = record_times(precision)
     dt = {CORR_FP32: np.float32, CORR_FP16: np.float16, CORR_INT8: np.int8}[precision]
-    a_pad = (N + 15) // 16 * 16 if (N + 15) // 16 <= 6 else (N + 63) // 64 * 64
-    ntq = ((S + tg - 1) // tg + 3) // 4 * 4
-    rec = np.asarray(buf).view(dt).reshape(K, ntq, a_pad, 2, tg)
-    t = np.arange(S)
-    re = rec[:, t // tg, :N, 0, t % tg]      # [S][K][N]
-    im = rec[:, t // tg, :N, 1, t % tg]
+    a_pad = a_pad_of(N)
+    ntq = ((S + tg - 1) // tg + TQB - 1) // TQB * TQB
+    rec = np.asarray(buf).view(dt)[: ntq * K * a_pad * 2 * tg].reshape(ntq // TQB, K, TQB, a_pad, 2, tg)
+    tq = np.arange(S) // tg
+    tb, tr, tt = tq // TQB, tq % TQB, np.arange(S) % tg
+    re = rec[tb, :, tr, :N, 0, tt]      # [S][K][N]
+    im = rec[tb, :, tr, :N, 1, tt]
     re = np.transpose(re, (0, 2, 1))
     im = np.transpose(im, (0, 2, 1))
     if precision == CORR_INT8:

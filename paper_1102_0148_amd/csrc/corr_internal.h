@@ -21,21 +21,30 @@ __host__ __device__ constexpr int record_times(int prec) {
 }
 __host__ __device__ constexpr int kblock_times(int prec) { return 4 * record_times(prec); }
 
+// Records are grouped in time blocks of kTQB consecutive records:
+// [time block][channel][kTQB records][antenna_pad].  The F-stage's writes of
+// one time block stay within K*kTQB*a_pad*16 bytes, and a channel's k-block
+// (4 records) is contiguous for the X-stage.
+constexpr int kTQB = 16;
+__host__ __device__ inline int64_t rec_index(int c, int tq, int a, int K, int a_pad) {
+    return (((int64_t)(tq / kTQB) * K + c) * kTQB + (tq % kTQB)) * a_pad + a;
+}
+
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 inline int64_t round_up64(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 // ---------------------------------------------------------------- F-stage
 struct FArgs {
     const uint8_t *in;        // chunk's frames [s][N][M bytes]
-    uint4 *spec;              // records [M][ntq][a_pad]
+    uint4 *spec;              // records, index rec_index(c, tq, a, M, a_pad)
     float *power;             // power mode: partial sums [nwg_per_group][a_pad][M]
     const float *scales;      // int8: [N][M]
     const float2 *tw;         // W_M^j (j < M), then W_2M^q (q < M/2)
     unsigned long long *sat;  // int8 saturation counter
     int N, a_pad, S;          // S = spectra in this chunk
-    int ntq;                  // records per channel and antenna in the buffer
+    int ntq;                  // power mode: time tiles in the window
     int ngroups;              // antenna groups of GA covering [0, N)
-    int ntiles;               // ntq * ngroups (normal) or power tiles
+    int ntiles;               // ntq_used * ngroups (normal mode)
     int tiles_per_wg;         // power mode: time tiles per workgroup
 };
 
@@ -44,11 +53,13 @@ struct FArgs {
 // (records not written).  Returns hipSuccess or the launch error.
 hipError_t launch_fstage(int M, int prec, int ga, int power_mode, const FArgs &a, int grid,
                          hipStream_t st);
-int fstage_lds_bytes(int M, int ga);
+int fstage_lds_bytes(int M, int prec, int ga);
+// antennas per tile that fill exactly one round of transforms
+int fstage_default_group(int M, int prec);
 
 // ---------------------------------------------------------------- X-stage
 struct XArgs {
-    const uint4 *spec;   // records [K][ntq][a_pad]
+    const uint4 *spec;   // records, index rec_index(c, tq, a, K, a_pad)
     void *partial;       // [nsplit][K][nb] float2 (fp32/fp16) or int2 (int8)
     const int2 *regions; // (I0, J0) block coordinates of each region
     int nregions;

@@ -24,7 +24,10 @@ namespace corr {
 namespace {
 
 constexpr int kThreads = 256;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kPowerTS = 2;
+// antennas per power-mode tile: one round of transforms
+constexpr int power_group(int M) { return (kThreads / (M / 16)) / kPowerTS; }
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
@@ -150,249 +153,280 @@ __device__ __forceinline__ float nib(uint32_t w, int off) {
     return (float)((int)(w << (28 - off)) >> 28);
 }
 
-template <int PREC>
-__device__ __forceinline__ void stage_store(void *stage, int rec, int ts, float re, float im, float sc,
-                                            unsigned &nsat) {
+// Pack TS spectra of one (channel, antenna) into a 16-byte record
+// [re x TS][im x TS] of the precision's type.  int8: q = clamp(rint(x sc)).
+template <int PREC, int TS>
+__device__ __forceinline__ uint4 make_record(const float *re, const float *im, float sc, unsigned &nsat) {
+    uint4 out;
     if constexpr (PREC == kFP32) {
-        float *s = reinterpret_cast<float *>(stage) + rec * 4;
-        s[ts] = re;
-        s[2 + ts] = im;
+        static_assert(TS == 2, "fp32 record");
+        out = make_uint4(__float_as_uint(re[0]), __float_as_uint(re[1]), __float_as_uint(im[0]),
+                         __float_as_uint(im[1]));
     } else if constexpr (PREC == kFP16) {
-        _Float16 *s = reinterpret_cast<_Float16 *>(stage) + rec * 8;
-        s[ts] = (_Float16)re;
-        s[4 + ts] = (_Float16)im;
+        static_assert(TS == 4, "fp16 record");
+        _Float16 h[8];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            h[t] = (_Float16)re[t];
+            h[4 + t] = (_Float16)im[t];
+        }
+        __builtin_memcpy(&out, h, 16);
     } else {
-        int8_t *s = reinterpret_cast<int8_t *>(stage) + rec * 16;
-        float vr = rintf(re * sc), vi = rintf(im * sc);
-        nsat += (fabsf(vr) > 127.0f) + (fabsf(vi) > 127.0f);
-        vr = fminf(fmaxf(vr, -127.0f), 127.0f);
-        vi = fminf(fmaxf(vi, -127.0f), 127.0f);
-        s[ts] = (int8_t)(int)vr;
-        s[8 + ts] = (int8_t)(int)vi;
+        static_assert(TS == 8, "int8 record");
+        int8_t b[16];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            float vr = rintf(re[t] * sc), vi = rintf(im[t] * sc);
+            nsat += (fabsf(vr) > 127.0f) + (fabsf(vi) > 127.0f);
+            b[t] = (int8_t)(int)fminf(fmaxf(vr, -127.0f), 127.0f);
+            b[8 + t] = (int8_t)(int)fminf(fmaxf(vi, -127.0f), 127.0f);
+        }
+        __builtin_memcpy(&out, b, 16);
+    }
+    return out;
+}
+
+// Real-input bins q and K-q (q = 0: bins 0 and K/2) from a transform slot.
+template <int M>
+__device__ __forceinline__ void real_bins(const float2 *zs, int q, const float2 *tw2, float2 &xlo,
+                                          float2 &xhi) {
+    if (q == 0) {
+        const float2 z0 = zs[0], zh = zs[pad(M / 2)];
+        xlo = make_float2(z0.x + z0.y, 0.0f);
+        xhi = make_float2(zh.x, -zh.y);
+    } else {
+        const float2 z0 = zs[pad(q)], z1 = zs[pad(M - q)];
+        const float2 A = make_float2(z0.x + z1.x, z0.y - z1.y);
+        const float2 B = make_float2(z0.x - z1.x, z0.y + z1.y);
+        const float2 C = cmul(B, tw2[q]);
+        xlo = make_float2(0.5f * (A.x + C.y), 0.5f * (A.y - C.x));
+        xhi = make_float2(0.5f * (A.x - C.y), 0.5f * (-A.y - C.x));
+    }
+}
+
+template <int M, int PREC, int GA, bool POWER>
+struct FShape {
+    static constexpr int L = M / 16;                  // lanes per transform
+    static constexpr int FPR = kThreads / L;          // transforms per round
+    static constexpr int SLOT = M + M / 16 + 1;       // padded float2 per transform
+    static constexpr int TS = POWER ? kPowerTS : record_times(PREC);
+    static constexpr int NF = TS * GA;                // transforms per tile
+    static constexpr int ROUNDS = (NF + FPR - 1) / FPR;
+    static constexpr int NTASK = (M / 2) * GA;        // (bin pair, antenna) tasks
+    static constexpr int TPT = (NTASK + kThreads - 1) / kThreads;
+    static constexpr int LDS = NF * SLOT * 8 + FPR * M;
+};
+
+// Transform the NF blocks of tile (tq, g) into zbuf slots (ts * GA + ga).
+template <int M, int GA, int TS, int NF, int ROUNDS>
+__device__ __forceinline__ void tile_ffts(const FArgs &args, int tq, int g, float2 *zbuf, uint32_t *bbuf,
+                                          const float2 *twM) {
+    constexpr int L = M / 16, FPR = kThreads / L, SLOT = M + M / 16 + 1;
+    const int fs = threadIdx.x / L, j = threadIdx.x % L;
+    uint32_t *bb = bbuf + fs * (M / 4);
+#pragma unroll 1
+    for (int r = 0; r < ROUNDS; ++r) {
+        const int fi = r * FPR + fs;
+        if (ROUNDS * FPR > NF && fi >= NF) break;  // idle transform slots of the last round
+        const int ts = fi / GA, ga = fi % GA;
+        const int s = tq * TS + ts, a = g * GA + ga;
+        float2 *z = zbuf + fi * SLOT;
+        u32x4 raw = {0u, 0u, 0u, 0u};
+        if (s < args.S && a < args.N)  // frames are read once: stream them past the caches
+            raw = __builtin_nontemporal_load(
+                reinterpret_cast<const u32x4 *>(args.in + ((int64_t)s * args.N + a) * M + 16 * j));
+        // dword d of the block goes to (d mod L/4)*16 + d div L/4, so the 16
+        // dwords pass 1 needs in a lane are contiguous
+        {
+            const uint32_t w[4] = {raw[0], raw[1], raw[2], raw[3]};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int d = 4 * j + c;
+                bb[(d % (L / 4)) * 16 + d / (L / 4)] = w[c];
+            }
+        }
+        wave_lds_sync();
+        // pass 1: radix 16 over z[j + r L], unpacked from the bytes
+        {
+            float2 v[16];
+            const uint4 *src = reinterpret_cast<const uint4 *>(bb + (j / 4) * 16);
+            const int off = 8 * (j & 3);
+#pragma unroll
+            for (int q4 = 0; q4 < 4; ++q4) {
+                const uint4 w4 = src[q4];
+                const uint32_t w[4] = {w4.x, w4.y, w4.z, w4.w};
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const uint32_t byte = w[c] >> off;
+                    v[4 * q4 + c] = make_float2(nib(byte, 0), nib(byte, 4));
+                }
+            }
+            dft16(v);
+#pragma unroll
+            for (int q = 0; q < 16; ++q) z[pad(16 * j + q)] = v[q];
+        }
+        wave_lds_sync();
+        if constexpr (M == 128) {
+            fft_pass<M, 8>(z, j, 16, twM);
+        } else {
+            fft_pass<M, 16>(z, j, 16, twM);
+            if constexpr (M == 512) {
+                wave_lds_sync();
+                fft_pass<M, 2>(z, j, 256, twM);
+            } else if constexpr (M == 1024) {
+                wave_lds_sync();
+                fft_pass<M, 4>(z, j, 256, twM);
+            }
+        }
+        wave_lds_sync();
     }
 }
 
 template <int M, int PREC, int GA, bool POWER>
 __global__ __launch_bounds__(kThreads) void fstage_kernel(FArgs args) {
-    constexpr int L = M / 16;                  // lanes per transform
-    constexpr int FPR = kThreads / L;          // transforms per round
-    constexpr int SLOT = M + M / 16 + 1;       // padded float2 per transform
-    constexpr int TS = POWER ? kPowerTS : record_times(PREC);
-    constexpr int NF = TS * GA;                // transforms per tile
-    constexpr int ROUNDS = (NF + FPR - 1) / FPR;
-    constexpr int NTASK = FPR * (M / 2);       // output pairs per round
-    static_assert(NTASK % kThreads == 0, "task split");
-    static_assert(16 % GA == 0, "group divides 16");
+    using Sh = FShape<M, PREC, GA, POWER>;
+    constexpr int TS = Sh::TS, NF = Sh::NF, SLOT = Sh::SLOT, NTASK = Sh::NTASK, TPT = Sh::TPT;
+    static_assert(Sh::LDS <= 160 * 1024, "LDS budget");
 
-    __shared__ float2 zbuf[FPR * SLOT];
-    __shared__ __attribute__((aligned(16))) uint32_t bbuf[FPR * (M / 4)];
-    __shared__ float2 tw[M + M / 2];
-    __shared__ uint4 stage[POWER ? 1 : M * GA];
-    __shared__ float pstage[POWER ? M * GA * TS : 1];
-    __shared__ float prun[POWER ? M * GA : 1];
-
+    __shared__ float2 zbuf[NF * SLOT];
+    __shared__ __attribute__((aligned(16))) uint32_t bbuf[Sh::FPR * (M / 4)];
     const int tid = threadIdx.x;
-    for (int i = tid; i < M + M / 2; i += kThreads) tw[i] = args.tw[i];
-    __syncthreads();
-    const float2 *twM = tw;
-    const float2 *tw2 = tw + M;
+    const float2 *twM = args.tw;
+    const float2 *tw2 = args.tw + M;
 
-    const int fs = tid / L;  // this lane's transform slot
-    const int j = tid % L;   // lane within the transform
-    float2 *z = zbuf + fs * SLOT;
-    uint32_t *bb = bbuf + fs * (M / 4);
-    unsigned nsat = 0;
-
-    int tile0 = blockIdx.x, tile1 = args.ntiles, tstep = gridDim.x;
-    int pg = 0, pw = 0;
-    if constexpr (POWER) {
-        // a workgroup owns a run of consecutive time tiles of one antenna group
-        const int nblk_t = (args.ntq + args.tiles_per_wg - 1) / args.tiles_per_wg;
-        pg = blockIdx.x / nblk_t;
-        pw = blockIdx.x % nblk_t;
-        tile0 = pw * args.tiles_per_wg;
-        tile1 = min(tile0 + args.tiles_per_wg, args.ntq);
-        tstep = 1;
-        for (int i = tid; i < M * GA; i += kThreads) prun[i] = 0.0f;
-        if (pg >= args.ngroups) return;
-    }
-
-    for (int tile = tile0; tile < tile1; tile += tstep) {
-        int tq, g;
-        if constexpr (POWER) {
-            tq = tile;
-            g = pg;
-        } else {
-            tq = tile / args.ngroups;
-            g = tile % args.ngroups;
-        }
-#pragma unroll 1
-        for (int r = 0; r < ROUNDS; ++r) {
-            const int fi = r * FPR + fs;
-            const int ts = fi / GA, ga = fi % GA;
-            const int s = tq * TS + ts, a = g * GA + ga;
-            const bool valid = fi < NF && s < args.S && a < args.N;
-            uint4 raw = make_uint4(0u, 0u, 0u, 0u);
-            if (valid)
-                raw = *reinterpret_cast<const uint4 *>(args.in + ((int64_t)s * args.N + a) * M + 16 * j);
-            // dword d of the block goes to (d mod L/4)*16 + d div L/4, so the
-            // 16 dwords pass 1 needs in a lane are contiguous
-            {
-                const uint32_t w[4] = {raw.x, raw.y, raw.z, raw.w};
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const int d = 4 * j + c;
-                    bb[(d % (L / 4)) * 16 + d / (L / 4)] = w[c];
-                }
-            }
-            wave_lds_sync();
-            // pass 1: radix 16 over z[j + r L], unpacked from the bytes
-            {
-                float2 v[16];
-                const uint4 *src = reinterpret_cast<const uint4 *>(bb + (j / 4) * 16);
-                const int off = 8 * (j & 3);
-#pragma unroll
-                for (int q4 = 0; q4 < 4; ++q4) {
-                    const uint4 w4 = src[q4];
-                    const uint32_t w[4] = {w4.x, w4.y, w4.z, w4.w};
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        const uint32_t byte = w[c] >> off;
-                        v[4 * q4 + c] = make_float2(nib(byte, 0), nib(byte, 4));
-                    }
-                }
-                dft16(v);
-#pragma unroll
-                for (int q = 0; q < 16; ++q) z[pad(16 * j + q)] = v[q];
-            }
-            wave_lds_sync();
-            if constexpr (M == 128) {
-                fft_pass<M, 8>(z, j, 16, twM);
-            } else {
-                fft_pass<M, 16>(z, j, 16, twM);
-                if constexpr (M == 512) {
-                    wave_lds_sync();
-                    fft_pass<M, 2>(z, j, 256, twM);
-                } else if constexpr (M == 1024) {
-                    wave_lds_sync();
-                    fft_pass<M, 4>(z, j, 256, twM);
-                }
-            }
-            __syncthreads();  // every slot's Z is complete
-
-            // real-input spectrum from Z[q], Z[M-q]; task (slot, q) gives two bins
-#pragma unroll 2
-            for (int it = 0; it < NTASK / kThreads; ++it) {
-                const int t = tid + it * kThreads;
-                const int sl = t % FPR;
-                const int q = t / FPR;
-                const int fi2 = r * FPR + sl;
-                if (fi2 >= NF) continue;
-                const int ts2 = fi2 / GA, ga2 = fi2 % GA;
-                const float2 *zs = zbuf + sl * SLOT;
-                float2 xlo, xhi;
-                int clo, chi;
-                if (q == 0) {
-                    const float2 z0 = zs[0], zh = zs[pad(M / 2)];
-                    xlo = make_float2(z0.x + z0.y, 0.0f);
-                    xhi = make_float2(zh.x, -zh.y);
-                    clo = 0;
-                    chi = M / 2;
-                } else {
-                    const float2 z0 = zs[pad(q)], z1 = zs[pad(M - q)];
-                    const float2 A = make_float2(z0.x + z1.x, z0.y - z1.y);
-                    const float2 B = make_float2(z0.x - z1.x, z0.y + z1.y);
-                    const float2 C = cmul(B, tw2[q]);
-                    xlo = make_float2(0.5f * (A.x + C.y), 0.5f * (A.y - C.x));
-                    xhi = make_float2(0.5f * (A.x - C.y), 0.5f * (-A.y - C.x));
-                    clo = q;
-                    chi = M - q;
-                }
-                if constexpr (POWER) {
-                    pstage[(clo * GA + ga2) * TS + ts2] = xlo.x * xlo.x + xlo.y * xlo.y;
-                    pstage[(chi * GA + ga2) * TS + ts2] = xhi.x * xhi.x + xhi.y * xhi.y;
-                } else {
-                    float slo = 1.0f, shi = 1.0f;
-                    if constexpr (PREC == kINT8) {
-                        const int a2 = g * GA + ga2;
-                        if (a2 < args.N) {
-                            slo = args.scales[(int64_t)a2 * M + clo];
-                            shi = args.scales[(int64_t)a2 * M + chi];
-                        }
-                    }
-                    stage_store<PREC>(stage, clo * GA + ga2, ts2, xlo.x, xlo.y, slo, nsat);
-                    stage_store<PREC>(stage, chi * GA + ga2, ts2, xhi.x, xhi.y, shi, nsat);
-                }
-            }
-            __syncthreads();  // stage complete; zbuf free for the next round
-        }
-        if constexpr (POWER) {
-            for (int i = tid; i < M * GA; i += kThreads) {
-                float acc = prun[i];
-#pragma unroll
-                for (int t2 = 0; t2 < TS; ++t2) acc += pstage[i * TS + t2];
-                prun[i] = acc;
-            }
-            // the next tile's first barrier orders these reads before new writes
-        } else {
-            // write-out: GA records of one channel are contiguous in global memory
-            for (int i = tid; i < M * GA; i += kThreads) {
-                const int c = i / GA, ga2 = i % GA;
-                args.spec[((int64_t)c * args.ntq + tq) * args.a_pad + g * GA + ga2] = stage[i];
-            }
-        }
-    }
-    if constexpr (POWER) {
+    if constexpr (!POWER) {
+        // one tile per workgroup; workgroups b, b+8, b+16, ... share an XCD
+        // (round-robin dispatch), so they take consecutive antenna groups of
+        // one time record and their partial lines meet in one L2
+        const int t8 = (args.ntiles + 7) / 8;
+        const int tile = (blockIdx.x % 8) * t8 + blockIdx.x / 8;
+        if (tile >= args.ntiles) return;
+        const int tq = tile / args.ngroups, g = tile % args.ngroups;
+        tile_ffts<M, GA, TS, NF, Sh::ROUNDS>(args, tq, g, zbuf, bbuf, twM);
         __syncthreads();
-        for (int i = tid; i < M * GA; i += kThreads) {
-            const int c = i / GA, ga2 = i % GA;
-            args.power[((int64_t)pw * args.a_pad + pg * GA + ga2) * M + c] = prun[i];
+        unsigned nsat = 0;
+#pragma unroll
+        for (int it = 0; it < TPT; ++it) {
+            const int t = tid + it * kThreads;
+            if (NTASK % kThreads != 0 && t >= NTASK) break;
+            const int ga = t % GA, q = t / GA;
+            const int a = g * GA + ga;
+            float lr[TS], li[TS], hr[TS], hi[TS];
+#pragma unroll
+            for (int ts = 0; ts < TS; ++ts) {
+                float2 xlo, xhi;
+                real_bins<M>(zbuf + (ts * GA + ga) * SLOT, q, tw2, xlo, xhi);
+                lr[ts] = xlo.x; li[ts] = xlo.y; hr[ts] = xhi.x; hi[ts] = xhi.y;
+            }
+            const int clo = q, chi = q == 0 ? M / 2 : M - q;
+            float slo = 1.0f, shi = 1.0f;
+            if constexpr (PREC == kINT8) {
+                if (a < args.N) {
+                    slo = args.scales[(int64_t)a * M + clo];
+                    shi = args.scales[(int64_t)a * M + chi];
+                }
+            }
+            const uint4 rlo = make_record<PREC, TS>(lr, li, slo, nsat);
+            const uint4 rhi = make_record<PREC, TS>(hr, hi, shi, nsat);
+            args.spec[rec_index(clo, tq, a, M, args.a_pad)] = rlo;
+            args.spec[rec_index(chi, tq, a, M, args.a_pad)] = rhi;
         }
-    }
-    if constexpr (PREC == kINT8 && !POWER) {
-        if (nsat) atomicAdd(args.sat, (unsigned long long)nsat);
+        if constexpr (PREC == kINT8) {
+            if (nsat) atomicAdd(args.sat, (unsigned long long)nsat);
+        }
+    } else {
+        // power sums over the calibration window: a workgroup owns a run of
+        // consecutive time tiles of one antenna group and keeps its sums in
+        // registers (fixed task -> thread mapping, fixed order)
+        const int nblk_t = (args.ntq + args.tiles_per_wg - 1) / args.tiles_per_wg;
+        const int pg = blockIdx.x / nblk_t, pw = blockIdx.x % nblk_t;
+        if (pg >= args.ngroups) return;
+        const int tile0 = pw * args.tiles_per_wg;
+        const int tile1 = min(tile0 + args.tiles_per_wg, args.ntq);
+        float plo[TPT], phi[TPT];
+#pragma unroll
+        for (int it = 0; it < TPT; ++it) plo[it] = phi[it] = 0.0f;
+        for (int tq = tile0; tq < tile1; ++tq) {
+            tile_ffts<M, GA, TS, NF, Sh::ROUNDS>(args, tq, pg, zbuf, bbuf, twM);
+            __syncthreads();
+#pragma unroll
+            for (int it = 0; it < TPT; ++it) {
+                const int t = tid + it * kThreads;
+                if (NTASK % kThreads != 0 && t >= NTASK) break;
+                const int ga = t % GA, q = t / GA;
+#pragma unroll
+                for (int ts = 0; ts < TS; ++ts) {
+                    float2 xlo, xhi;
+                    real_bins<M>(zbuf + (ts * GA + ga) * SLOT, q, tw2, xlo, xhi);
+                    plo[it] += xlo.x * xlo.x + xlo.y * xlo.y;
+                    phi[it] += xhi.x * xhi.x + xhi.y * xhi.y;
+                }
+            }
+            __syncthreads();  // zbuf is rewritten by the next tile
+        }
+#pragma unroll
+        for (int it = 0; it < TPT; ++it) {
+            const int t = tid + it * kThreads;
+            if (NTASK % kThreads != 0 && t >= NTASK) break;
+            const int ga = t % GA, q = t / GA;
+            const int a = pg * GA + ga;
+            const int clo = q, chi = q == 0 ? M / 2 : M - q;
+            float *pw_row = args.power + ((int64_t)pw * args.a_pad + a) * M;
+            pw_row[clo] = plo[it];
+            pw_row[chi] = phi[it];
+        }
     }
 }
 
 template <int M, int PREC, int GA, bool POWER>
 hipError_t launch_one(const FArgs &a, int grid, hipStream_t st) {
-    hipLaunchKernelGGL((fstage_kernel<M, PREC, GA, POWER>), dim3(grid), dim3(kThreads), 0, st, a);
-    return hipGetLastError();
+    if constexpr (FShape<M, PREC, GA, POWER>::LDS > 160 * 1024) {
+        return hipErrorInvalidValue;
+    } else {
+        hipLaunchKernelGGL((fstage_kernel<M, PREC, GA, POWER>), dim3(grid), dim3(kThreads), 0, st, a);
+        return hipGetLastError();
+    }
+}
+
+template <int M, int PREC>
+hipError_t launch_mp(int ga, int power, const FArgs &a, int grid, hipStream_t st) {
+    if (power) return launch_one<M, kFP32, power_group(M), true>(a, grid, st);
+    switch (ga) {
+        case 1: return launch_one<M, PREC, 1, false>(a, grid, st);
+        case 2: return launch_one<M, PREC, 2, false>(a, grid, st);
+        case 4: return launch_one<M, PREC, 4, false>(a, grid, st);
+        case 8: return launch_one<M, PREC, 8, false>(a, grid, st);
+        case 16: return launch_one<M, PREC, 16, false>(a, grid, st);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <int M>
 hipError_t launch_m(int prec, int ga, int power, const FArgs &a, int grid, hipStream_t st) {
-    if (power) return launch_one<M, kFP32, 4, true>(a, grid, st);
-    switch (prec * 16 + ga) {
-        case kFP32 * 16 + 2: return launch_one<M, kFP32, 2, false>(a, grid, st);
-        case kFP32 * 16 + 4: return launch_one<M, kFP32, 4, false>(a, grid, st);
-        case kFP16 * 16 + 2: return launch_one<M, kFP16, 2, false>(a, grid, st);
-        case kFP16 * 16 + 4: return launch_one<M, kFP16, 4, false>(a, grid, st);
-        case kINT8 * 16 + 2: return launch_one<M, kINT8, 2, false>(a, grid, st);
-        case kINT8 * 16 + 4: return launch_one<M, kINT8, 4, false>(a, grid, st);
-        default: break;
-    }
-    if constexpr (M <= 512) {
-        switch (prec) {
-            case kFP32: return launch_one<M, kFP32, 8, false>(a, grid, st);
-            case kFP16: return launch_one<M, kFP16, 8, false>(a, grid, st);
-            case kINT8: return launch_one<M, kINT8, 8, false>(a, grid, st);
-        }
+    switch (prec) {
+        case kFP32: return launch_mp<M, kFP32>(ga, power, a, grid, st);
+        case kFP16: return launch_mp<M, kFP16>(ga, power, a, grid, st);
+        case kINT8: return launch_mp<M, kINT8>(ga, power, a, grid, st);
     }
     return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-int fstage_lds_bytes(int M, int ga) {
+int fstage_lds_bytes(int M, int prec, int ga) {
     const int L = M / 16, FPR = kThreads / L, SLOT = M + M / 16 + 1;
-    return FPR * SLOT * 8 + FPR * M + (M + M / 2) * 8 + M * ga * 16;
+    return record_times(prec) * ga * SLOT * 8 + FPR * M;
+}
+
+int fstage_default_group(int M, int prec) {
+    const int fpr = kThreads / (M / 16);
+    const int g = fpr / record_times(prec);
+    return g < 1 ? 1 : g;
 }
 
 hipError_t launch_fstage(int M, int prec, int ga, int power_mode, const FArgs &a, int grid,
                          hipStream_t st) {
-    if (ga != 2 && ga != 4 && ga != 8) return hipErrorInvalidValue;
-    if (M == 1024 && ga == 8 && !power_mode) return hipErrorInvalidValue;
+    if (!power_mode && fstage_lds_bytes(M, prec, ga) > 160 * 1024) return hipErrorInvalidValue;
     switch (M) {
         case 128: return launch_m<128>(prec, ga, power_mode, a, grid, st);
         case 256: return launch_m<256>(prec, ga, power_mode, a, grid, st);

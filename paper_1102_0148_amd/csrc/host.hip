@@ -135,6 +135,9 @@ struct corr_ctx {
 
 namespace {
 
+// time tiles (2 spectra each) per workgroup of the calibration power sums
+constexpr int kCalibTilesPerWG = 4;
+
 int check_shape(int N, int K, int S) {
     if (N < 2 || N > CORR_MAX_ANTENNAS) return fail(CORR_EINVAL, "N=%d out of [2, %d]", N, CORR_MAX_ANTENNAS);
     if (!is_pow2(K) || K < CORR_MIN_CHANNELS || K > CORR_MAX_CHANNELS)
@@ -161,13 +164,14 @@ void free_ctx(corr_ctx *h) {
 
 int default_chunk(const corr_ctx *h) {
     const int64_t per_spectrum = (int64_t)h->a_pad * h->K * (kRecordBytes / h->TG);
-    const int64_t cap_bytes = (int64_t)1 << 30;
+    // the whole integration when it fits in 8 GB of scratch: fewer, longer
+    // X-stage launches beat the small cache-resident chunks measured on MI355X
+    const int64_t cap_bytes = (int64_t)8 << 30;
     int64_t c = std::max<int64_t>(64, cap_bytes / per_spectrum / 64 * 64);
     c = std::min<int64_t>(c, round_up64(h->S, 64));
     return (int)c;
 }
 
-int default_group(int K) { return K >= 1024 ? 4 : 8; }
 
 int n_regions(const corr_ctx *h) { return h->n_diag + h->n_off; }
 
@@ -189,10 +193,13 @@ int plan(corr_ctx *h) {
     HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
     h->TG = record_times(h->prec);
     if (h->tiles.chunk_spectra == 0) h->tiles.chunk_spectra = default_chunk(h);
-    if (h->tiles.f_group == 0) h->tiles.f_group = default_group(h->K);
+    if (h->tiles.f_group == 0) h->tiles.f_group = fstage_default_group(h->K, h->prec);
     if (h->tiles.x_splits == 0) h->tiles.x_splits = default_splits(h);
+    if (fstage_lds_bytes(h->K, h->prec, h->tiles.f_group) > 160 * 1024)
+        return fail(CORR_EINVAL, "f_group=%d needs more than 160 KB of LDS at K=%d in this precision",
+                    h->tiles.f_group, h->K);
     const int chunk = h->tiles.chunk_spectra;
-    h->ntq_buf = round_up((chunk + h->TG - 1) / h->TG, 4);
+    h->ntq_buf = round_up((chunk + h->TG - 1) / h->TG, kTQB);
     h->spec_bytes = (size_t)h->K * h->ntq_buf * h->a_pad * kRecordBytes;
     HIP_TRY(hipMalloc(&h->spec, h->spec_bytes), "hipMalloc(spectra chunk)");
     HIP_TRY(hipMemset(h->spec, 0, h->spec_bytes), "hipMemset(spectra chunk)");
@@ -200,7 +207,7 @@ int plan(corr_ctx *h) {
     if (h->prec == kINT8) {
         const int W = std::min(h->S, CORR_CALIB_SPECTRA);
         const int ntq_w = (W + 1) / 2;
-        const int nparts = (ntq_w + 31) / 32;
+        const int nparts = (ntq_w + kCalibTilesPerWG - 1) / kCalibTilesPerWG;
         HIP_TRY(hipMalloc(&h->scales, (size_t)h->N * h->K * sizeof(float)), "hipMalloc(scales)");
         HIP_TRY(hipMalloc(&h->power, (size_t)nparts * h->a_pad * h->K * sizeof(float)), "hipMalloc(power)");
     }
@@ -212,9 +219,11 @@ int check_tiles(const corr_ctx *h, const corr_tiles *t) {
     if (t->chunk_spectra < 0 || (t->chunk_spectra % 64) != 0)
         return fail(CORR_EINVAL, "chunk_spectra=%d must be a non-negative multiple of 64", t->chunk_spectra);
     if (t->x_splits < 0 || t->x_splits > 64) return fail(CORR_EINVAL, "x_splits=%d out of [0, 64]", t->x_splits);
-    if (t->f_group != 0 && t->f_group != 2 && t->f_group != 4 && t->f_group != 8)
-        return fail(CORR_EINVAL, "f_group=%d must be 0, 2, 4 or 8", t->f_group);
-    if (t->f_group == 8 && h->K >= 1024) return fail(CORR_EINVAL, "f_group=8 needs K <= 512");
+    if (t->f_group != 0 && t->f_group != 1 && t->f_group != 2 && t->f_group != 4 && t->f_group != 8 &&
+        t->f_group != 16)
+        return fail(CORR_EINVAL, "f_group=%d must be 0, 1, 2, 4, 8 or 16", t->f_group);
+    if (t->f_group && fstage_lds_bytes(h->K, h->prec, t->f_group) > 160 * 1024)
+        return fail(CORR_EINVAL, "f_group=%d needs more than 160 KB of LDS at K=%d", t->f_group, h->K);
     return CORR_OK;
 }
 
@@ -283,13 +292,14 @@ int calibrate(corr_ctx *h, const uint8_t *in, hipStream_t st) {
     fa.N = h->N;
     fa.a_pad = h->a_pad;
     fa.S = W;
-    fa.ntq = (W + 1) / 2;
-    fa.ngroups = (h->N + 3) / 4;
-    fa.tiles_per_wg = 32;
-    const int nparts = (fa.ntq + 31) / 32;
+    fa.ntq = (W + 1) / 2;  // power-mode tiles hold 2 spectra
+    const int gp = (256 / (h->K / 16)) / 2;  // antennas per power-mode tile
+    fa.ngroups = (h->N + gp - 1) / gp;
+    fa.tiles_per_wg = kCalibTilesPerWG;
+    const int nparts = (fa.ntq + kCalibTilesPerWG - 1) / kCalibTilesPerWG;
     fa.ntiles = fa.ntq;
     timer_begin(h, 0, st);
-    HIP_TRY(launch_fstage(h->K, kFP32, 4, 1, fa, fa.ngroups * nparts, st), "calibration launch");
+    HIP_TRY(launch_fstage(h->K, kFP32, gp, 1, fa, fa.ngroups * nparts, st), "calibration launch");
     HIP_TRY(launch_scales(h->power, nparts, h->N, h->a_pad, h->K, W, h->scales, st), "scales launch");
     timer_end(h, st);
     return CORR_OK;
@@ -321,7 +331,7 @@ int process_one(corr_ctx *h, const uint8_t *in, hipStream_t st) {
         fa.ntq = h->ntq_buf;
         fa.ngroups = ngroups;
         fa.ntiles = ntq_used * ngroups;
-        const int grid = std::min(fa.ntiles, 8192);
+        const int grid = 8 * ((fa.ntiles + 7) / 8);  // one tile per workgroup
         timer_begin(h, 1, st);
         HIP_TRY(launch_fstage(h->K, h->prec, ga, 0, fa, grid, st), "F-stage launch");
         timer_end(h, st);
@@ -483,7 +493,6 @@ int corr_process(corr_handle hh, const void *packed, void *stream) {
     rc = process_one(h, (const uint8_t *)packed, st);
     if (rc) return rc;
     h->accumulated += h->S;
-    if (h->timing) return timers_collect(h);
     return CORR_OK;
 }
 
@@ -529,7 +538,7 @@ size_t corr_spectra_bytes(corr_handle hh, int n_spectra) {
     corr_ctx *h = single(hh);
     if (!h || n_spectra < 1) return 0;
     const int tg = record_times(h->prec);
-    const int ntq = round_up((n_spectra + tg - 1) / tg, 4);
+    const int ntq = round_up((n_spectra + tg - 1) / tg, kTQB);
     return (size_t)h->K * ntq * h->a_pad * kRecordBytes;
 }
 
@@ -549,7 +558,6 @@ int corr_process_spectra(corr_handle hh, const void *spectra, int n_spectra, voi
     rc = launch_x_and_dump(h, (const uint4 *)spectra, ntq, ntq / 4, st);
     if (rc) return rc;
     h->accumulated += n_spectra;
-    if (h->timing) return timers_collect(h);
     return CORR_OK;
 }
 
@@ -560,10 +568,9 @@ int corr_debug_read_spectra(corr_handle hh, void *out, int *n_spectra) {
     *n_spectra = h->last_chunk;
     if (!out) return CORR_OK;
     HIP_TRY(hipStreamSynchronize(h->last_stream), "hipStreamSynchronize");
-    const int ntq = round_up((h->last_chunk + h->TG - 1) / h->TG, 4);
-    const size_t row = (size_t)ntq * h->a_pad * kRecordBytes;
-    const size_t pitch = (size_t)h->ntq_buf * h->a_pad * kRecordBytes;
-    HIP_TRY(hipMemcpy2D(out, row, h->spec, pitch, row, h->K, hipMemcpyDeviceToHost), "hipMemcpy2D(spectra)");
+    // time blocks are outermost, so the chunk's records are a prefix
+    const size_t bytes = corr_spectra_bytes(hh, h->last_chunk);
+    HIP_TRY(hipMemcpy(out, h->spec, bytes, hipMemcpyDeviceToHost), "hipMemcpy(spectra)");
     return CORR_OK;
 }
 

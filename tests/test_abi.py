@@ -65,14 +65,14 @@ def test_record_layout_round_trip(prec, N, S):
             spec = spec.real.astype(np.float16).astype(np.float32) + 1j * spec.imag.astype(np.float16).astype(np.float32)
     buf = corr.spectra_to_records(spec, prec)
     tg = corr.record_times(prec)
-    a_pad = (N + 15) // 16 * 16 if (N + 15) // 16 <= 6 else (N + 63) // 64 * 64
-    ntq = ((S + tg - 1) // tg + 3) // 4 * 4
+    a_pad = corr.a_pad_of(N)
+    ntq = ((S + tg - 1) // tg + 15) // 16 * 16
     assert buf.size == K * ntq * a_pad * 16
     back = corr.records_to_spectra(buf, prec, N, K, S)
     np.testing.assert_array_equal(back, spec)
     # one record by hand: channel 3, antenna 2, spectra 0..tg-1 as [re x tg][im x tg]
     dt = {corr.CORR_FP32: np.float32, corr.CORR_FP16: np.float16, corr.CORR_INT8: np.int8}[prec]
-    rec = buf.view(dt).reshape(K, -1, a_pad, 2 * tg)[3, 0, 2]
+    rec = buf.view(dt).reshape(-1, K, 16, a_pad, 2 * tg)[0, 3, 0, 2]
     n = min(tg, S)
     if prec == corr.CORR_INT8:
         np.testing.assert_array_equal(rec[:n], spec[:n, 2, 3, 0])
