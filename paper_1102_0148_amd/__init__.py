@@ -367,3 +367,55 @@ def records_to_spectra(buf: np.ndarray, precision: int, N: int, K: int, S: int) 
     if precision == CORR_INT8:
         return np.stack([re, im], axis=-1)
     return re.astype(np.float32) + 1j * im.astype(np.float32)
+
+
+class Batch:
+    """Many correlations of different shapes in one persistent kernel launch,
+    replayed from a captured HIP graph.  jobs: list of (N, K, n_spectra,
+    precision); tiles: optional {job index: {"x_splits": s}}."""
+
+    def __init__(self, jobs, tiles: Optional[dict] = None):
+        self.jobs = [(int(N), int(K), int(S), PRECISIONS[p] if isinstance(p, str) else int(p))
+                     for (N, K, S, p) in jobs]
+        self.h = corr_batch_create(self.jobs)
+        try:
+            for j, t in (tiles or {}).items():
+                corr_batch_set_tiles(self.h, j, **t)
+        except Exception:
+            self.close()
+            raise
+
+    def close(self):
+        if getattr(self, "h", None):
+            corr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def process(self, packed_list, stream=None):
+        assert len(packed_list) == len(self.jobs)
+        for (N, K, S, _), x in zip(self.jobs, packed_list):
+            assert x.is_cuda and x.numel() == S * N * K
+        corr_batch_process(self.h, [x.data_ptr() for x in packed_list], _stream(stream))
+
+    def read_cps_raw(self, j: int) -> np.ndarray:
+        N, K, _, _ = self.jobs[j]
+        out = np.empty((n_baselines(N), K, 2), dtype=np.float64)
+        corr_batch_read_cps_raw(self.h, j, _np_ptr(out))
+        return out
+
+    def read_cps(self, j: int) -> np.ndarray:
+        N, K, _, _ = self.jobs[j]
+        out = np.empty((n_baselines(N), K, 2), dtype=np.float32)
+        corr_batch_read_cps(self.h, j, _np_ptr(out))
+        return out[..., 0] + 1j * out[..., 1]
+
+    def read_scales(self, j: int) -> np.ndarray:
+        N, K, _, _ = self.jobs[j]
+        out = np.empty((N, K), dtype=np.float32)
+        corr_batch_read_scales(self.h, j, _np_ptr(out))
+        return out

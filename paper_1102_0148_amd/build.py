@@ -13,10 +13,11 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libcorr.so")
-SOURCES = ["host.hip", "fstage.hip", "xstage.hip", "dump.hip"]
+SOURCES = ["host.hip", "fstage.hip", "xstage.hip", "dump.hip", "batch.hip"]
 ARCH = "gfx950"
-# Packed fp32 VALU forms are kept out of every kernel on this target.
-FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
+# Packed fp32 VALU forms are kept out of every kernel on this target, and
+# floating-point contraction is off: fused multiply-adds are written out.
+FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-Wno-unused-result"]
 

@@ -31,6 +31,14 @@ __host__ __device__ inline int64_t rec_index(int c, int tq, int a, int K, int a_
 }
 
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+// Orders this wavefront's LDS writes before its later LDS reads.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 inline int64_t round_up64(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 // ---------------------------------------------------------------- F-stage
@@ -81,5 +89,46 @@ hipError_t launch_scales(const float *power, int nparts, int N, int a_pad, int K
 // dst[bl][f] = acc[f][bl] (raw layout), then acc = 0.
 hipError_t launch_finalize(double2 *acc, double2 *dst, int K, int nb, hipStream_t st);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st);
+
+// ---------------------------------------------------------------- batch
+// One correlation job of a batch, as the persistent kernel sees it.  F-stage
+// tiles use the group that fills one round of transforms; X regions are at
+// most 3 blocks on a side (diagonal) or 2 (off the diagonal).
+struct BJob {
+    FArgs f;             // records (f.in is taken from the call's pointer table)
+    FArgs p;             // calibration power sums (int8)
+    XArgs xd, xo;        // X-stage over the diagonal / off-diagonal regions
+    double2 *acc;        // integration buffer [K][nb]
+    float *scales;
+    int K, prec, rb_d, rb_o;
+    int n_acc;           // K * nb
+    int W, nparts;       // calibration window and power partials
+    int sc_n;            // N * K scale entries
+};
+
+// A work item; `wait` counter must reach wait_val before the item runs and
+// `sig` counter is incremented when it is done (-1: none).
+enum { BI_POWER = 0, BI_SCALES, BI_F, BI_XD, BI_XO, BI_DUMP };
+struct BItem {
+    int type, job;
+    int a0, a1;          // power block | scale range | tile range | X workgroup | dump range
+    int wait, wait_val, sig, pad;
+};
+constexpr int kBatchCounters = 5;  // per job: power, scales, F, X, dump
+
+// Items per tile range, elements per scale / dump item.
+constexpr int kBatchTilesPerItem = 4;
+constexpr int kBatchElemsPerItem = 2048;
+// spin limit of a dependency wait (about a second); past it the kernel
+// records an error and goes on, so every wave always exits
+constexpr unsigned kBatchSpinLimit = 1u << 22;
+
+int batch_default_group(int M, int prec);
+int batch_lds_bytes(int M, int prec);
+hipError_t batch_prepare(int lds_bytes);
+int batch_max_blocks(int lds_bytes);
+hipError_t launch_batch(const BJob *jobs, const uint8_t *const *in_ptrs, const BItem *items, int n_items,
+                        unsigned *ticket, unsigned *ctr, unsigned *err, int grid, int lds_bytes,
+                        hipStream_t st);
 
 }  // namespace corr

@@ -1,41 +1,21 @@
-// Integration-buffer kernels: the float64 dump of tile partials (Section 1:
-// the cross power spectra are accumulated to the required cadence), the int8
+// Integration-buffer kernels: the float64 dump of tile partials, the int8
 // calibration scales, the read-out transpose and a plain fill.
-#include "corr_internal.h"
+#include "dump_dev.h"
 
 namespace corr {
 namespace {
 
-// acc[e] += partial[0][e] + partial[1][e] + ... in this order, in float64.
 template <typename P>
 __global__ __launch_bounds__(256) void dump_kernel(const P *partial, double2 *acc, int nsplit,
                                                    int64_t n) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= n) return;
-    double2 v = acc[e];
-    for (int s = 0; s < nsplit; ++s) {
-        const P p = partial[(int64_t)s * n + e];
-        v.x += (double)p.x;
-        v.y += (double)p.y;
-    }
-    acc[e] = v;
+    if (e < n) dump_one<P>(partial, acc, nsplit, n, e);
 }
 
-// rms over the window per component: sqrt(P / (2W)); scale = 127 / (4 rms);
-// a channel with no power keeps scale 1.
 __global__ __launch_bounds__(256) void scales_kernel(const float *power, int nparts, int N, int a_pad,
                                                      int K, int W, float *scales) {
     const int e = blockIdx.x * 256 + threadIdx.x;
-    if (e >= N * K) return;
-    const int ant = e / K, c = e % K;
-    float p = 0.0f;
-    for (int i = 0; i < nparts; ++i) p += power[((int64_t)i * a_pad + ant) * K + c];
-    float sc = 1.0f;
-    if (p > 0.0f) {
-        const float rms = sqrtf(p / (2.0f * (float)W));
-        sc = 127.0f / (4.0f * rms);
-    }
-    scales[e] = sc;
+    if (e < N * K) scales[e] = scale_one(power, nparts, a_pad, K, W, e);
 }
 
 // dst[bl][f] = acc[f][bl]; acc = 0

@@ -1,0 +1,38 @@
+// Float64 dump of tile partials and int8 scales, as device functions shared
+// by the single-job kernels and the batch kernel.
+#pragma once
+#include "corr_internal.h"
+
+namespace corr {
+namespace {
+
+// acc[e] += partial[0][e] + partial[1][e] + ... in this order, in float64
+// (Section 1: the cross power spectra are accumulated to the cadence).
+template <typename P>
+__device__ __forceinline__ void dump_one(const P *partial, double2 *acc, int nsplit, int64_t n, int64_t e) {
+    double2 v = acc[e];
+    for (int s = 0; s < nsplit; ++s) {
+        const P p = partial[(int64_t)s * n + e];
+        v.x += (double)p.x;
+        v.y += (double)p.y;
+    }
+    acc[e] = v;
+}
+
+// Scale of (antenna, channel) e = ant * K + c: the power over the window is
+// summed over its nparts partials in order; rms per component is
+// sqrt(P / (2W)); scale = 127 / (4 rms); a channel with no power keeps 1.
+__device__ __forceinline__ float scale_one(const float *power, int nparts, int a_pad, int K, int W, int e) {
+    const int ant = e / K, c = e % K;
+    float p = 0.0f;
+    for (int i = 0; i < nparts; ++i) p += power[((int64_t)i * a_pad + ant) * K + c];
+    float sc = 1.0f;
+    if (p > 0.0f) {
+        const float rms = sqrtf(p / (2.0f * (float)W));
+        sc = 127.0f / (4.0f * rms);
+    }
+    return sc;
+}
+
+}  // namespace
+}  // namespace corr

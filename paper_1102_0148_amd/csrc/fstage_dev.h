@@ -1,0 +1,387 @@
+// F-stage of the FX correlator: unpack 4-bit samples, 2K-point real FFT,
+// corner turn to channel-major records, conversion to the X-stage precision.
+//
+// What is computed (Section 1, Section 4 of Prasad & Subrahmanya): for each
+// spectrum s and antenna a, X[s,a,k] = sum_n x[n] exp(-2 pi i k n / 2K),
+// k = 0..K-1, forward and unnormalised, no window.
+//
+// How (gfx950): the 2K real samples of a block are read as K complex values
+// z[m] = x[2m] + i x[2m+1] -- one byte of the frame is exactly one z[m], low
+// nibble the real part.  A K-point complex FFT runs as Stockham passes of
+// radix 16 (then 8, 4 or 2) over a padded LDS slot, 16 points per lane and
+// K/16 lanes per transform, so every exchange inside one transform stays in
+// one wavefront.  The real-input spectrum follows from Z[q] and Z[K-q]:
+//   X[q] = (Z[q] + conj Z[K-q])/2 - (i/2) W_2K^q (Z[q] - conj Z[K-q]).
+// Twiddles come from a host table with exact 0, +-1 and +-sqrt(1/2) entries,
+// and the paths to bins 0 and K/2 only ever multiply by 1, so those two bins
+// are exact (they are Gaussian integers).  A tile is TS consecutive spectra
+// of GA consecutive antennas; its outputs are staged in LDS and written as
+// 16-byte records [re x TS][im x TS], GA records (GA*16 bytes) contiguous
+// per channel.  Power mode sums |X|^2 over the calibration window instead.
+#pragma once
+#include "corr_internal.h"
+
+namespace corr {
+namespace {
+
+constexpr int kThreads = 256;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kPowerTS = 2;
+// antennas per power-mode tile: one round of transforms
+constexpr int power_group(int M) { return (kThreads / (M / 16)) / kPowerTS; }
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+// Every product-sum is written with explicit fmaf (the library is built with
+// contraction off), so a transform rounds the same way in every kernel that
+// inlines it and results do not depend on tile choices.
+__device__ __forceinline__ float2 cmul(float2 a, float2 w) {
+    return make_float2(fmaf(a.x, w.x, -(a.y * w.y)), fmaf(a.x, w.y, a.y * w.x));
+}
+// -i * a
+__device__ __forceinline__ float2 mul_mi(float2 a) { return make_float2(a.y, -a.x); }
+
+// exact constants of the 16th roots of unity
+constexpr float kC1 = 0.923879532511286756f;  // cos(pi/8)
+constexpr float kS1 = 0.382683432365089772f;  // sin(pi/8)
+constexpr float kR = 0.707106781186547524f;   // sqrt(1/2)
+
+__device__ __forceinline__ void dft2(float2 &a, float2 &b) {
+    float2 t = a;
+    a = cadd(t, b);
+    b = csub(t, b);
+}
+
+__device__ __forceinline__ void dft4(float2 &a0, float2 &a1, float2 &a2, float2 &a3) {
+    float2 s02 = cadd(a0, a2), d02 = csub(a0, a2);
+    float2 s13 = cadd(a1, a3), d13 = mul_mi(csub(a1, a3));
+    a0 = cadd(s02, s13);
+    a2 = csub(s02, s13);
+    a1 = cadd(d02, d13);
+    a3 = csub(d02, d13);
+}
+
+// 16-point DFT as 4 x 4: x[4 n1 + n2], k = k1 + 4 k2; output in natural order.
+__device__ __forceinline__ void dft16(float2 *v) {
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) dft4(v[n2], v[4 + n2], v[8 + n2], v[12 + n2]);
+    // v[4 k1 + n2] = A[n2][k1]; multiply by W16^(n2 k1)
+    v[5] = make_float2(fmaf(kC1, v[5].x, kS1 * v[5].y), fmaf(kC1, v[5].y, -(kS1 * v[5].x)));      // W^1
+    v[6] = make_float2(kR * (v[6].x + v[6].y), kR * (v[6].y - v[6].x));                // W^2
+    v[7] = make_float2(fmaf(kS1, v[7].x, kC1 * v[7].y), fmaf(kS1, v[7].y, -(kC1 * v[7].x)));      // W^3
+    v[9] = make_float2(kR * (v[9].x + v[9].y), kR * (v[9].y - v[9].x));                // W^2
+    v[10] = mul_mi(v[10]);                                                              // W^4
+    v[11] = make_float2(kR * (v[11].y - v[11].x), -kR * (v[11].x + v[11].y));          // W^6
+    v[13] = make_float2(fmaf(kS1, v[13].x, kC1 * v[13].y), fmaf(kS1, v[13].y, -(kC1 * v[13].x))); // W^3
+    v[14] = make_float2(kR * (v[14].y - v[14].x), -kR * (v[14].x + v[14].y));          // W^6
+    v[15] = make_float2(fmaf(-kC1, v[15].x, -(kS1 * v[15].y)), fmaf(kS1, v[15].x, -(kC1 * v[15].y))); // W^9
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) dft4(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+    // now v[4 k1 + k2] = X[k1 + 4 k2]: transpose the 4 x 4 index
+    float2 t[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) t[k] = v[4 * (k & 3) + (k >> 2)];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = t[k];
+}
+
+// 8-point DFT as 2 x 4: x[4 n1 + n2], k = k1 + 2 k2; output in natural order.
+__device__ __forceinline__ void dft8(float2 *v) {
+    float2 a[4][2];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+        a[n2][0] = cadd(v[n2], v[4 + n2]);
+        a[n2][1] = csub(v[n2], v[4 + n2]);
+    }
+    a[1][1] = make_float2(kR * (a[1][1].x + a[1][1].y), kR * (a[1][1].y - a[1][1].x));  // W8^1
+    a[2][1] = mul_mi(a[2][1]);                                                            // W8^2
+    a[3][1] = make_float2(kR * (a[3][1].y - a[3][1].x), -kR * (a[3][1].x + a[3][1].y));  // W8^3
+#pragma unroll
+    for (int k1 = 0; k1 < 2; ++k1) {
+        dft4(a[0][k1], a[1][k1], a[2][k1], a[3][k1]);
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) v[k1 + 2 * k2] = a[k2][k1];
+    }
+}
+
+template <int R>
+__device__ __forceinline__ void dft_r(float2 *v) {
+    if constexpr (R == 16) dft16(v);
+    else if constexpr (R == 8) dft8(v);
+    else if constexpr (R == 4) dft4(v[0], v[1], v[2], v[3]);
+    else dft2(v[0], v[1]);
+}
+
+// LDS index with one float2 of padding every 16 (bank spreading)
+__device__ __forceinline__ int pad(int e) { return e + (e >> 4); }
+
+
+// Stockham pass of radix R (p = product of the radices before it), in place
+// in one transform's LDS slot.  Butterfly i reads z[i + r M/R], multiplies by
+// W_{pR}^{r k} (k = i mod p), and writes z[(i - k) R + k + r p].
+template <int M, int R>
+__device__ __forceinline__ void fft_pass(float2 *z, int j, int p, const float2 *twM) {
+    constexpr int L = M / 16;
+    constexpr int T = M / R;
+    constexpr int NBF = 16 / R;
+    float2 v[16];
+#pragma unroll
+    for (int m = 0; m < NBF; ++m) {
+        const int i = j + L * m;
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[m * R + r] = z[pad(i + r * T)];
+    }
+    wave_lds_sync();  // every read of this pass precedes every write
+#pragma unroll
+    for (int m = 0; m < NBF; ++m) {
+        const int i = j + L * m;
+        const int k = i & (p - 1);
+        const int step = k * (M / (p * R));
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[m * R + r] = cmul(v[m * R + r], twM[(r * step) & (M - 1)]);
+        dft_r<R>(&v[m * R]);
+        const int base = (i - k) * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) z[pad(base + r * p)] = v[m * R + r];
+    }
+}
+
+// Signed nibble at bit offset `off` of w.
+__device__ __forceinline__ float nib(uint32_t w, int off) {
+    return (float)((int)(w << (28 - off)) >> 28);
+}
+
+// Pack TS spectra of one (channel, antenna) into a 16-byte record
+// [re x TS][im x TS] of the precision's type.  int8: q = clamp(rint(x sc)).
+template <int PREC, int TS>
+__device__ __forceinline__ uint4 make_record(const float *re, const float *im, float sc, unsigned &nsat) {
+    uint4 out;
+    if constexpr (PREC == kFP32) {
+        static_assert(TS == 2, "fp32 record");
+        out = make_uint4(__float_as_uint(re[0]), __float_as_uint(re[1]), __float_as_uint(im[0]),
+                         __float_as_uint(im[1]));
+    } else if constexpr (PREC == kFP16) {
+        static_assert(TS == 4, "fp16 record");
+        _Float16 h[8];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            h[t] = (_Float16)re[t];
+            h[4 + t] = (_Float16)im[t];
+        }
+        __builtin_memcpy(&out, h, 16);
+    } else {
+        static_assert(TS == 8, "int8 record");
+        int8_t b[16];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            float vr = rintf(re[t] * sc), vi = rintf(im[t] * sc);
+            nsat += (fabsf(vr) > 127.0f) + (fabsf(vi) > 127.0f);
+            b[t] = (int8_t)(int)fminf(fmaxf(vr, -127.0f), 127.0f);
+            b[8 + t] = (int8_t)(int)fminf(fmaxf(vi, -127.0f), 127.0f);
+        }
+        __builtin_memcpy(&out, b, 16);
+    }
+    return out;
+}
+
+// Real-input bins q and K-q (q = 0: bins 0 and K/2) from a transform slot.
+template <int M>
+__device__ __forceinline__ void real_bins(const float2 *zs, int q, const float2 *tw2, float2 &xlo,
+                                          float2 &xhi) {
+    if (q == 0) {
+        const float2 z0 = zs[0], zh = zs[pad(M / 2)];
+        xlo = make_float2(z0.x + z0.y, 0.0f);
+        xhi = make_float2(zh.x, -zh.y);
+    } else {
+        const float2 z0 = zs[pad(q)], z1 = zs[pad(M - q)];
+        const float2 A = make_float2(z0.x + z1.x, z0.y - z1.y);
+        const float2 B = make_float2(z0.x - z1.x, z0.y + z1.y);
+        const float2 C = cmul(B, tw2[q]);
+        xlo = make_float2(0.5f * (A.x + C.y), 0.5f * (A.y - C.x));
+        xhi = make_float2(0.5f * (A.x - C.y), 0.5f * (-A.y - C.x));
+    }
+}
+
+template <int M, int PREC, int GA, bool POWER>
+struct FShape {
+    static constexpr int L = M / 16;                  // lanes per transform
+    static constexpr int FPR = kThreads / L;          // transforms per round
+    static constexpr int SLOT = M + M / 16 + 1;       // padded float2 per transform
+    static constexpr int TS = POWER ? kPowerTS : record_times(PREC);
+    static constexpr int NF = TS * GA;                // transforms per tile
+    static constexpr int ROUNDS = (NF + FPR - 1) / FPR;
+    static constexpr int NTASK = (M / 2) * GA;        // (bin pair, antenna) tasks
+    static constexpr int TPT = (NTASK + kThreads - 1) / kThreads;
+    static constexpr int LDS = NF * SLOT * 8 + FPR * M;
+};
+
+// Transform the NF blocks of tile (tq, g) into zbuf slots (ts * GA + ga).
+template <int M, int GA, int TS, int NF, int ROUNDS>
+__device__ __forceinline__ void tile_ffts(const FArgs &args, int tq, int g, float2 *zbuf, uint32_t *bbuf,
+                                          const float2 *twM) {
+    constexpr int L = M / 16, FPR = kThreads / L, SLOT = M + M / 16 + 1;
+    const int fs = threadIdx.x / L, j = threadIdx.x % L;
+    uint32_t *bb = bbuf + fs * (M / 4);
+#pragma unroll 1
+    for (int r = 0; r < ROUNDS; ++r) {
+        const int fi = r * FPR + fs;
+        if (ROUNDS * FPR > NF && fi >= NF) break;  // idle transform slots of the last round
+        const int ts = fi / GA, ga = fi % GA;
+        const int s = tq * TS + ts, a = g * GA + ga;
+        float2 *z = zbuf + fi * SLOT;
+        u32x4 raw = {0u, 0u, 0u, 0u};
+        if (s < args.S && a < args.N)  // frames are read once: stream them past the caches
+            raw = __builtin_nontemporal_load(
+                reinterpret_cast<const u32x4 *>(args.in + ((int64_t)s * args.N + a) * M + 16 * j));
+        // dword d of the block goes to (d mod L/4)*16 + d div L/4, so the 16
+        // dwords pass 1 needs in a lane are contiguous
+        {
+            const uint32_t w[4] = {raw[0], raw[1], raw[2], raw[3]};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int d = 4 * j + c;
+                bb[(d % (L / 4)) * 16 + d / (L / 4)] = w[c];
+            }
+        }
+        wave_lds_sync();
+        // pass 1: radix 16 over z[j + r L], unpacked from the bytes
+        {
+            float2 v[16];
+            const uint4 *src = reinterpret_cast<const uint4 *>(bb + (j / 4) * 16);
+            const int off = 8 * (j & 3);
+#pragma unroll
+            for (int q4 = 0; q4 < 4; ++q4) {
+                const uint4 w4 = src[q4];
+                const uint32_t w[4] = {w4.x, w4.y, w4.z, w4.w};
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const uint32_t byte = w[c] >> off;
+                    v[4 * q4 + c] = make_float2(nib(byte, 0), nib(byte, 4));
+                }
+            }
+            dft16(v);
+#pragma unroll
+            for (int q = 0; q < 16; ++q) z[pad(16 * j + q)] = v[q];
+        }
+        wave_lds_sync();
+        if constexpr (M == 128) {
+            fft_pass<M, 8>(z, j, 16, twM);
+        } else {
+            fft_pass<M, 16>(z, j, 16, twM);
+            if constexpr (M == 512) {
+                wave_lds_sync();
+                fft_pass<M, 2>(z, j, 256, twM);
+            } else if constexpr (M == 1024) {
+                wave_lds_sync();
+                fft_pass<M, 4>(z, j, 256, twM);
+            }
+        }
+        wave_lds_sync();
+    }
+}
+
+// One tile (time record tq, antenna group g) of spectra records: TS spectra
+// of GA antennas transformed, turned into bins and written as records.  The
+// caller separates consecutive calls with a workgroup barrier.
+template <int M, int PREC, int GA>
+__device__ __forceinline__ void f_tile(const FArgs &args, int tile, float2 *zbuf, uint32_t *bbuf) {
+    using Sh = FShape<M, PREC, GA, false>;
+    constexpr int TS = Sh::TS, SLOT = Sh::SLOT, NTASK = Sh::NTASK, TPT = Sh::TPT;
+    const int tid = threadIdx.x;
+    const float2 *twM = args.tw;
+    const float2 *tw2 = args.tw + M;
+    const int tq = tile / args.ngroups, g = tile % args.ngroups;
+    tile_ffts<M, GA, TS, Sh::NF, Sh::ROUNDS>(args, tq, g, zbuf, bbuf, twM);
+    __syncthreads();
+    unsigned nsat = 0;
+#pragma unroll
+    for (int it = 0; it < TPT; ++it) {
+        const int t = tid + it * kThreads;
+        if (NTASK % kThreads != 0 && t >= NTASK) break;
+        const int ga = t % GA, q = t / GA;
+        const int a = g * GA + ga;
+        float lr[TS], li[TS], hr[TS], hi[TS];
+#pragma unroll
+        for (int ts = 0; ts < TS; ++ts) {
+            float2 xlo, xhi;
+            real_bins<M>(zbuf + (ts * GA + ga) * SLOT, q, tw2, xlo, xhi);
+            lr[ts] = xlo.x; li[ts] = xlo.y; hr[ts] = xhi.x; hi[ts] = xhi.y;
+        }
+        const int clo = q, chi = q == 0 ? M / 2 : M - q;
+        float slo = 1.0f, shi = 1.0f;
+        if constexpr (PREC == kINT8) {
+            if (a < args.N) {
+                slo = args.scales[(int64_t)a * M + clo];
+                shi = args.scales[(int64_t)a * M + chi];
+            }
+        }
+        const uint4 rlo = make_record<PREC, TS>(lr, li, slo, nsat);
+        const uint4 rhi = make_record<PREC, TS>(hr, hi, shi, nsat);
+        args.spec[rec_index(clo, tq, a, M, args.a_pad)] = rlo;
+        args.spec[rec_index(chi, tq, a, M, args.a_pad)] = rhi;
+    }
+    if constexpr (PREC == kINT8) {
+        if (nsat) atomicAdd(args.sat, (unsigned long long)nsat);
+    }
+}
+
+// Power sums over the calibration window for block blk = group * nblk_t +
+// time block: a run of tiles_per_wg consecutive time tiles of one antenna
+// group, sums kept in registers (fixed task -> thread mapping, fixed order).
+template <int M>
+__device__ __forceinline__ void f_power_block(const FArgs &args, int blk, float2 *zbuf, uint32_t *bbuf) {
+    constexpr int GA = power_group(M);
+    using Sh = FShape<M, kFP32, GA, true>;
+    constexpr int TS = Sh::TS, SLOT = Sh::SLOT, NTASK = Sh::NTASK, TPT = Sh::TPT;
+    const int tid = threadIdx.x;
+    const float2 *twM = args.tw;
+    const float2 *tw2 = args.tw + M;
+    const int nblk_t = (args.ntq + args.tiles_per_wg - 1) / args.tiles_per_wg;
+    const int pg = blk / nblk_t, pw = blk % nblk_t;
+    if (pg >= args.ngroups) return;
+    const int tile0 = pw * args.tiles_per_wg;
+    const int tile1 = min(tile0 + args.tiles_per_wg, args.ntq);
+    float plo[TPT], phi[TPT];
+#pragma unroll
+    for (int it = 0; it < TPT; ++it) plo[it] = phi[it] = 0.0f;
+    for (int tq = tile0; tq < tile1; ++tq) {
+        tile_ffts<M, GA, TS, Sh::NF, Sh::ROUNDS>(args, tq, pg, zbuf, bbuf, twM);
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < TPT; ++it) {
+            const int t = tid + it * kThreads;
+            if (NTASK % kThreads != 0 && t >= NTASK) break;
+            const int ga = t % GA, q = t / GA;
+#pragma unroll
+            for (int ts = 0; ts < TS; ++ts) {
+                float2 xlo, xhi;
+                real_bins<M>(zbuf + (ts * GA + ga) * SLOT, q, tw2, xlo, xhi);
+                plo[it] += fmaf(xlo.x, xlo.x, xlo.y * xlo.y);
+                phi[it] += fmaf(xhi.x, xhi.x, xhi.y * xhi.y);
+            }
+        }
+        __syncthreads();  // zbuf is rewritten by the next tile
+    }
+#pragma unroll
+    for (int it = 0; it < TPT; ++it) {
+        const int t = tid + it * kThreads;
+        if (NTASK % kThreads != 0 && t >= NTASK) break;
+        const int ga = t % GA, q = t / GA;
+        const int a = pg * GA + ga;
+        const int clo = q, chi = q == 0 ? M / 2 : M - q;
+        float *pw_row = args.power + ((int64_t)pw * args.a_pad + a) * M;
+        pw_row[clo] = plo[it];
+        pw_row[chi] = phi[it];
+    }
+}
+
+// LDS bytes a tile of (M, PREC, GA) needs: transform slots, then (16-byte
+// aligned) the byte staging of one round.
+template <int M, int PREC, int GA, bool POWER>
+constexpr int f_lds_bytes() {
+    using Sh = FShape<M, PREC, GA, POWER>;
+    return (Sh::NF * Sh::SLOT * 8 + 15) / 16 * 16 + Sh::FPR * (M / 4) * 4;
+}
+
+}  // namespace
+}  // namespace corr

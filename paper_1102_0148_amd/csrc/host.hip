@@ -129,8 +129,17 @@ struct corr_ctx {
     double ms[4] = {0, 0, 0, 0};  // calib, F, X, dump
     int64_t launches_f = 0, launches_x = 0;
     std::vector<Timer> timers;
-    // batch
+    // batch: the jobs, their device descriptors, the work list, counters
+    // (ticket, error flag, then kBatchCounters per job) and the captured graph
     std::vector<corr_ctx *> jobs;
+    BJob *bjobs = nullptr;
+    const uint8_t **in_ptrs = nullptr;
+    BItem *items = nullptr;
+    unsigned *bctr = nullptr;
+    int n_items = 0, n_ctr = 0, b_grid = 0, b_lds = 0;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
 };
 
 namespace {
@@ -155,7 +164,11 @@ void free_ctx(corr_ctx *h) {
         hipEventDestroy(t.a);
         hipEventDestroy(t.b);
     }
-    void *bufs[] = {h->spec, h->partial, h->acc, h->stage, h->tw, h->scales, h->power, h->regions, h->sat};
+    if (h->gexec) hipGraphExecDestroy(h->gexec);
+    if (h->graph) hipGraphDestroy(h->graph);
+    if (h->cap_stream) hipStreamDestroy(h->cap_stream);
+    void *bufs[] = {h->spec,   h->partial, h->acc,   h->stage,   h->tw,   h->scales, h->power,
+                    h->regions, h->sat,    h->bjobs, h->in_ptrs, h->items, h->bctr};
     for (void *p : bufs)
         if (p) hipFree(p);
     for (corr_ctx *j : h->jobs) free_ctx(j);
@@ -382,6 +395,27 @@ int descale_to_float(corr_ctx *h, const double *raw, float *out) {
     return CORR_OK;
 }
 
+// Tile the triangle of 16-antenna block pairs with regions of rb x rb blocks:
+// the diagonal regions first, then the off-diagonal ones.
+hipError_t set_regions(corr_ctx *h, int rb) {
+    std::vector<int2> regs;
+    const int nr = h->nblk / rb;
+    for (int i = 0; i < nr; ++i) regs.push_back(make_int2(i * rb, i * rb));
+    const int n_diag = (int)regs.size();
+    for (int i = 0; i < nr; ++i)
+        for (int j = i + 1; j < nr; ++j) regs.push_back(make_int2(i * rb, j * rb));
+    if (h->regions) hipFree(h->regions);
+    h->regions = nullptr;
+    hipError_t e = hipMalloc(&h->regions, regs.size() * sizeof(int2));
+    if (e != hipSuccess) return e;
+    e = hipMemcpy(h->regions, regs.data(), regs.size() * sizeof(int2), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return e;
+    h->rb = rb;
+    h->n_diag = n_diag;
+    h->n_off = (int)regs.size() - n_diag;
+    return hipSuccess;
+}
+
 corr_ctx *create_ctx(int N, int K, int S) {
     if (check_shape(N, K, S)) return nullptr;
     corr_ctx *h = new (std::nothrow) corr_ctx();
@@ -409,17 +443,7 @@ corr_ctx *create_ctx(int N, int K, int S) {
     };
     hipError_t e = hipGetDevice(&h->device);
     if (e != hipSuccess) return bail(e, "hipGetDevice");
-    // regions of the block triangle
-    std::vector<int2> regs;
-    const int nr = h->nblk / h->rb;
-    for (int i = 0; i < nr; ++i) regs.push_back(make_int2(i * h->rb, i * h->rb));
-    h->n_diag = (int)regs.size();
-    for (int i = 0; i < nr; ++i)
-        for (int j = i + 1; j < nr; ++j) regs.push_back(make_int2(i * h->rb, j * h->rb));
-    h->n_off = (int)regs.size() - h->n_diag;
-    if ((e = hipMalloc(&h->regions, regs.size() * sizeof(int2))) != hipSuccess) return bail(e, "hipMalloc(regions)");
-    if ((e = hipMemcpy(h->regions, regs.data(), regs.size() * sizeof(int2), hipMemcpyHostToDevice)) != hipSuccess)
-        return bail(e, "hipMemcpy(regions)");
+    if ((e = set_regions(h, h->rb)) != hipSuccess) return bail(e, "regions");
     // twiddles: W_K^j, j < K, then W_2K^q, q < K/2
     std::vector<float2> tw((size_t)K + K / 2);
     for (int j = 0; j < K; ++j) tw[j] = twiddle(j, K);
@@ -616,35 +640,239 @@ void corr_destroy(corr_handle h) { free_ctx(h); }
 // ------------------------------------------------------------------- batch
 
 corr_handle corr_batch_create(const corr_job *jobs, int n_jobs) {
-    (void)jobs;
-    (void)n_jobs;
-    fail(CORR_EINVAL, "batch mode is not available in this build");
-    return nullptr;
+    g_err[0] = 0;
+    if (!jobs || n_jobs < 1 || n_jobs > 64) {
+        fail(CORR_EINVAL, "n_jobs=%d out of [1, 64]", n_jobs);
+        return nullptr;
+    }
+    corr_ctx *b = new (std::nothrow) corr_ctx();
+    if (!b) {
+        fail(CORR_ENOMEM, "host allocation failed");
+        return nullptr;
+    }
+    b->batch = true;
+    if (hipGetDevice(&b->device) != hipSuccess) {
+        fail(CORR_EHIP, "hipGetDevice failed");
+        delete b;
+        return nullptr;
+    }
+    for (int i = 0; i < n_jobs; ++i) {
+        const corr_job &jd = jobs[i];
+        corr_ctx *h = create_ctx(jd.N, jd.K, jd.n_spectra);
+        if (h) b->jobs.push_back(h);
+        if (!h || corr_set_precision(h, jd.precision) != CORR_OK) {
+            char msg[512];
+            snprintf(msg, sizeof msg, "job %d: %s", i, g_err);
+            free_ctx(b);
+            fail(CORR_EINVAL, "%s", msg);
+            return nullptr;
+        }
+    }
+    return b;
 }
 
 int corr_batch_set_tiles(corr_handle b, int job, const corr_tiles *t) {
-    (void)b; (void)job; (void)t;
-    return fail(CORR_EINVAL, "batch mode is not available in this build");
+    if (!b || !b->batch || !t) return fail(CORR_EINVAL, "invalid batch handle or tiles");
+    if (job < 0 || job >= (int)b->jobs.size()) return fail(CORR_EINVAL, "job %d out of range", job);
+    if (b->gexec) return fail(CORR_ESTATE, "tiles are fixed once the batch has run");
+    corr_ctx *h = b->jobs[job];
+    const int whole = round_up(h->S, 64);
+    if (t->chunk_spectra != 0 && t->chunk_spectra != whole)
+        return fail(CORR_EINVAL, "a batch job is one chunk: chunk_spectra must be 0 or %d", whole);
+    const int g = batch_default_group(h->K, h->prec);
+    if (t->f_group != 0 && t->f_group != g)
+        return fail(CORR_EINVAL, "a batch job uses f_group %d for K=%d in this precision", g, h->K);
+    if (t->x_splits < 0 || t->x_splits > 64) return fail(CORR_EINVAL, "x_splits=%d out of [0, 64]", t->x_splits);
+    h->tiles.x_splits = t->x_splits;
+    return CORR_OK;
 }
+
+namespace {
+
+// Plan every job as one chunk, lay out the work list and capture the graph.
+int batch_build(corr_ctx *b) {
+    HIP_TRY(hipSetDevice(b->device), "hipSetDevice");
+    const int nj = (int)b->jobs.size();
+    std::vector<BJob> bj(nj);
+    std::vector<BItem> power, scales, fitems, xitems, dumps;
+    int lds = 0;
+    for (int j = 0; j < nj; ++j) {
+        corr_ctx *h = b->jobs[j];
+        h->tiles.chunk_spectra = round_up(h->S, 64);
+        h->tiles.f_group = batch_default_group(h->K, h->prec);
+        int rc = plan(h);
+        if (rc) return rc;
+        // regions small enough for the batch kernel's register budget
+        const int rb = h->nblk <= 3 ? h->nblk : (h->nblk % 2 == 0 ? 2 : 1);
+        HIP_TRY(set_regions(h, rb), "regions");
+        lds = std::max(lds, batch_lds_bytes(h->K, h->prec));
+        const int c0 = 2 + j * kBatchCounters;  // power, scales, F, X, dump
+        const int ga = h->tiles.f_group;
+        const int ngroups = (h->N + ga - 1) / ga;
+        const int ntq_used = round_up((h->S + h->TG - 1) / h->TG, 4);
+        BJob &d = bj[j];
+        std::memset(&d, 0, sizeof d);
+        d.f.spec = h->spec;
+        d.f.scales = h->scales;
+        d.f.tw = h->tw;
+        d.f.sat = h->sat;
+        d.f.N = h->N;
+        d.f.a_pad = h->a_pad;
+        d.f.S = h->S;
+        d.f.ntq = h->ntq_buf;
+        d.f.ngroups = ngroups;
+        d.f.ntiles = ntq_used * ngroups;
+        XArgs xa{};
+        xa.spec = h->spec;
+        xa.partial = h->partial;
+        xa.N = h->N;
+        xa.a_pad = h->a_pad;
+        xa.K = h->K;
+        xa.ntq = h->ntq_buf;
+        xa.nb = h->nb;
+        xa.nsplit = h->tiles.x_splits;
+        xa.nkb = ntq_used / 4;
+        d.xd = xa;
+        d.xd.regions = h->regions;
+        d.xd.nregions = h->n_diag;
+        d.xo = xa;
+        d.xo.regions = h->regions + h->n_diag;
+        d.xo.nregions = h->n_off;
+        d.acc = h->acc;
+        d.scales = h->scales;
+        d.K = h->K;
+        d.prec = h->prec;
+        d.rb_d = rb;
+        d.rb_o = rb;
+        d.n_acc = h->K * h->nb;
+        d.sc_n = h->N * h->K;
+        int n_scales = 0;
+        if (h->prec == kINT8) {
+            const int W = std::min(h->S, CORR_CALIB_SPECTRA);
+            const int gp = (256 / (h->K / 16)) / 2;
+            d.p.power = h->power;
+            d.p.tw = h->tw;
+            d.p.N = h->N;
+            d.p.a_pad = h->a_pad;
+            d.p.S = W;
+            d.p.ntq = (W + 1) / 2;
+            d.p.ngroups = (h->N + gp - 1) / gp;
+            d.p.tiles_per_wg = kCalibTilesPerWG;
+            d.W = W;
+            d.nparts = (d.p.ntq + kCalibTilesPerWG - 1) / kCalibTilesPerWG;
+            const int n_power = d.p.ngroups * d.nparts;
+            for (int i = 0; i < n_power; ++i) power.push_back(BItem{BI_POWER, j, i, 0, -1, 0, c0 + 0, 0});
+            for (int e = 0; e < d.sc_n; e += kBatchElemsPerItem, ++n_scales)
+                scales.push_back(BItem{BI_SCALES, j, e, std::min(e + kBatchElemsPerItem, d.sc_n), c0 + 0, n_power,
+                                       c0 + 1, 0});
+        }
+        int n_f = 0;
+        for (int t = 0; t < d.f.ntiles; t += kBatchTilesPerItem, ++n_f)
+            fitems.push_back(BItem{BI_F, j, t, std::min(t + kBatchTilesPerItem, d.f.ntiles),
+                                   h->prec == kINT8 ? c0 + 1 : -1, n_scales, c0 + 2, 0});
+        const int wd = (h->n_diag * h->K * xa.nsplit + 3) / 4, wo = (h->n_off * h->K * xa.nsplit + 3) / 4;
+        for (int x = 0; x < wd; ++x) xitems.push_back(BItem{BI_XD, j, x, 0, c0 + 2, n_f, c0 + 3, 0});
+        for (int x = 0; x < wo; ++x) xitems.push_back(BItem{BI_XO, j, x, 0, c0 + 2, n_f, c0 + 3, 0});
+        for (int e = 0; e < d.n_acc; e += kBatchElemsPerItem)
+            dumps.push_back(BItem{BI_DUMP, j, e, std::min(e + kBatchElemsPerItem, d.n_acc), c0 + 3, wd + wo,
+                                  c0 + 4, 0});
+    }
+    std::vector<BItem> items;
+    for (auto *v : {&power, &scales, &fitems, &xitems, &dumps}) items.insert(items.end(), v->begin(), v->end());
+    b->n_items = (int)items.size();
+    b->n_ctr = 2 + nj * kBatchCounters;
+    b->b_lds = lds;
+    HIP_TRY(batch_prepare(lds), "hipFuncSetAttribute(batch)");
+    const int maxb = batch_max_blocks(lds);
+    if (maxb < 1) return fail(CORR_EHIP, "the batch kernel does not fit on this device (LDS %d bytes)", lds);
+    b->b_grid = std::min(maxb, b->n_items);
+    HIP_TRY(hipMalloc(&b->bjobs, nj * sizeof(BJob)), "hipMalloc(batch jobs)");
+    HIP_TRY(hipMemcpy(b->bjobs, bj.data(), nj * sizeof(BJob), hipMemcpyHostToDevice), "hipMemcpy(batch jobs)");
+    HIP_TRY(hipMalloc(&b->items, items.size() * sizeof(BItem)), "hipMalloc(batch items)");
+    HIP_TRY(hipMemcpy(b->items, items.data(), items.size() * sizeof(BItem), hipMemcpyHostToDevice),
+            "hipMemcpy(batch items)");
+    HIP_TRY(hipMalloc(&b->in_ptrs, nj * sizeof(uint8_t *)), "hipMalloc(batch inputs)");
+    const size_t ctr_bytes = (size_t)round_up(b->n_ctr * (int)sizeof(unsigned), 16);
+    HIP_TRY(hipMalloc(&b->bctr, ctr_bytes), "hipMalloc(batch counters)");
+    HIP_TRY(hipMemset(b->bctr, 0, ctr_bytes), "hipMemset(batch counters)");
+    // the graph: clear ticket, error flag and counters, then the persistent kernel
+    HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+    HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    hipError_t e1 = launch_fill_zero(b->bctr, ctr_bytes, b->cap_stream);
+    hipError_t e2 = launch_batch(b->bjobs, b->in_ptrs, b->items, b->n_items, b->bctr, b->bctr + 2, b->bctr + 1,
+                                 b->b_grid, lds, b->cap_stream);
+    HIP_TRY(hipStreamEndCapture(b->cap_stream, &b->graph), "hipStreamEndCapture");
+    HIP_TRY(e1, "batch counter clear");
+    HIP_TRY(e2, "batch kernel launch");
+    HIP_TRY(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+    return CORR_OK;
+}
+
+corr_ctx *batch_job(corr_handle b, int job) {
+    if (!b || !b->batch || job < 0 || job >= (int)b->jobs.size()) return nullptr;
+    return b->jobs[job];
+}
+
+int batch_check_error(corr_ctx *b) {
+    unsigned err = 0;
+    HIP_TRY(hipMemcpy(&err, b->bctr + 1, sizeof err, hipMemcpyDeviceToHost), "hipMemcpy(batch error)");
+    if (err) return fail(CORR_EHIP, "batch: a dependency wait exceeded its limit; results are invalid");
+    return CORR_OK;
+}
+
+}  // namespace
 
 int corr_batch_process(corr_handle b, const void *const *packed, void *stream) {
-    (void)b; (void)packed; (void)stream;
-    return fail(CORR_EINVAL, "batch mode is not available in this build");
-}
-
-int corr_batch_read_cps(corr_handle b, int job, float *out) {
-    (void)b; (void)job; (void)out;
-    return fail(CORR_EINVAL, "batch mode is not available in this build");
+    if (!b || !b->batch || !packed) return fail(CORR_EINVAL, "invalid batch handle or pointer table");
+    const int nj = (int)b->jobs.size();
+    for (int j = 0; j < nj; ++j) {
+        if (!packed[j] || (reinterpret_cast<uintptr_t>(packed[j]) & 15))
+            return fail(CORR_EINVAL, "job %d: packed samples must be a 16-byte aligned device pointer", j);
+        if (b->jobs[j]->prec == kINT8 && b->jobs[j]->accumulated)
+            return fail(CORR_ESTATE, "job %d (INT8): read the previous integration first", j);
+    }
+    if (!b->gexec) {
+        int rc = batch_build(b);
+        if (rc) return rc;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    // pageable source: the copy is staged before this call returns
+    HIP_TRY(hipMemcpyAsync(b->in_ptrs, packed, nj * sizeof(void *), hipMemcpyHostToDevice, st),
+            "hipMemcpyAsync(batch inputs)");
+    HIP_TRY(hipGraphLaunch(b->gexec, st), "hipGraphLaunch");
+    b->last_stream = st;
+    for (corr_ctx *h : b->jobs) {
+        h->started = true;
+        h->last_stream = st;
+        h->accumulated += h->S;
+        h->last_chunk = h->S;
+    }
+    return CORR_OK;
 }
 
 int corr_batch_read_cps_raw(corr_handle b, int job, double *out) {
-    (void)b; (void)job; (void)out;
-    return fail(CORR_EINVAL, "batch mode is not available in this build");
+    corr_ctx *h = batch_job(b, job);
+    if (!h) return fail(CORR_EINVAL, "invalid batch handle or job");
+    int rc = read_raw_into(h, out);
+    if (rc) return rc;
+    return batch_check_error(b);
+}
+
+int corr_batch_read_cps(corr_handle b, int job, float *out) {
+    corr_ctx *h = batch_job(b, job);
+    if (!h || !out) return fail(CORR_EINVAL, "invalid batch handle, job or out");
+    std::vector<double> raw((size_t)h->nb * h->K * 2);
+    int rc = read_raw_into(h, raw.data());
+    if (rc) return rc;
+    rc = batch_check_error(b);
+    if (rc) return rc;
+    return descale_to_float(h, raw.data(), out);
 }
 
 int corr_batch_read_scales(corr_handle b, int job, float *out) {
-    (void)b; (void)job; (void)out;
-    return fail(CORR_EINVAL, "batch mode is not available in this build");
+    corr_ctx *h = batch_job(b, job);
+    if (!h) return fail(CORR_EINVAL, "invalid batch handle or job");
+    return corr_read_scales(h, out);
 }
 
 }  // extern "C"

@@ -219,10 +219,32 @@ def test_int8_x_stage_on_oracle_spectra(N, K, S):
 def test_int8_tile_invariance_exact():
     N, K, S = 44, 256, 700
     outs = []
-    for tiles in (dict(chunk_spectra=64, x_splits=1, f_group=2), dict(chunk_spectra=704, x_splits=7, f_group=8)):
+    for tiles in (dict(chunk_spectra=64, x_splits=1, f_group=2), dict(chunk_spectra=704, x_splits=7, f_group=8),
+                  dict(chunk_spectra=128, x_splits=3, f_group=1)):
         _, _, _, _, _, raw = _int8_run(N, K, S, seed=3, tiles=tiles)
         outs.append(raw)
     np.testing.assert_array_equal(outs[0], outs[1])
+    np.testing.assert_array_equal(outs[0], outs[2])
+
+
+@pytest.mark.parametrize("prec,groups", [("fp32", (1, 2, 4, 8, 16)), ("fp16", (1, 2, 4, 8)),
+                                         ("int8", (1, 2, 4, 8))])
+def test_fstage_bit_identical_across_groups(prec, groups):
+    """The F-stage's arithmetic is fully specified (explicit fused
+    multiply-adds), so every tile shape gives the same bits."""
+    N, K, S = 44, 256, 300
+    packed = _packed(synth.recipe_tone(N=N, two_k=2 * K, seed=3), S)
+    ref = None
+    for g in groups:
+        c = corr.Correlator(N, K, S, precision=prec, tiles=dict(chunk_spectra=320, f_group=g))
+        c.process(packed)
+        buf, n = c.debug_read_spectra()
+        c.read_cps_raw()
+        sp = corr.records_to_spectra(buf, corr.PRECISIONS[prec], N, K, n)
+        if ref is None:
+            ref = sp
+        else:
+            np.testing.assert_array_equal(sp, ref)
 
 
 def test_int8_physical_units_match_fp64():
