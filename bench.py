@@ -38,6 +38,29 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCES = {"fstage_kernel<256, 0, 8, false>": ("fstage_dev.h", "fstage.hip", "corr_internal.h"),
+                  "xstage_kernel<0, 3, true>": ("xstage_dev.h", "xstage.hip", "corr_internal.h")}
+
+
+def measured_traffic(kernel, spectra_per_launch):
+    """HBM bytes per launch from the committed rocprofv3 counter runs
+    (profiles/traffic.json), or None when the kernel's source has changed since
+    the counters were taken or the launch covers a different number of spectra."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    entry = json.load(open(path)).get(kernel)
+    if entry is None or f"{spectra_per_launch} spectra" not in entry.get("workload", ""):
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        h.update(open(os.path.join(ROOT, "paper_1102_0148_amd", "csrc", f), "rb").read())
+    if h.hexdigest() != entry["source_sha256"]:
+        return None
+    return entry["fetch_bytes"] + entry["write_bytes"]
+
+
 def make_inputs(device):
     import synth
     recipe = synth.recipe_plain(N=N_ANT, two_k=TWO_K, rho=0.05, seed=1)
@@ -49,7 +72,7 @@ def make_inputs(device):
 
 
 def run_form(corr, torch, precision, inputs, steps, warmup, timing=False):
-    c = corr.Correlator(N_ANT, K, S_INT, precision=precision)
+    c = corr.Correlator(N_ANT, K, S_INT, precision=precision, tiles="auto")
     dst = torch.empty(c.nb * K * 2, dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
 
@@ -102,6 +125,79 @@ def accuracy(corr, torch, precision):
     return err
 
 
+def large_n(corr, torch, metrics, steps, warmup):
+    """N = 256 antennas, 1024-point FFT -> 512 channels, 16384 spectra with
+    three delayed point sources: the X-stage-dominated case, int8 vs fp32."""
+    import synth
+    N, two_k, S = 256, 1024, 16384
+    Kc = two_k // 2
+    x = synth.packed(synth.recipe_sources(N=N, two_k=two_k, seed=4), 0, S, device="cuda").contiguous()
+    out = {"workload": f"N={N}, {two_k}-pt FFT -> {Kc} channels, {S} spectra, 3 delayed sources"}
+    for prec in ("fp32", "int8"):
+        c = corr.Correlator(N, Kc, S, precision=prec, tiles="auto")
+        dst = torch.empty(c.nb * Kc * 2, dtype=torch.float64, device="cuda")
+        for _ in range(warmup):
+            c.process(x); c.read_cps_async(dst)
+        c.enable_timing(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            c.process(x); c.read_cps_async(dst)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        st = c.stats()
+        x_ms = st["ms_x"] / steps
+        out[prec] = {"antenna_msps": round(metrics.antenna_samples(N, two_k, S) / (ms * 1e-3) / 1e6, 1),
+                     "ms_per_integration": round(ms, 4),
+                     "x_tops": round(metrics.x_ops(N, Kc, S) / (x_ms * 1e-3) / 1e12, 2),
+                     "ms_f": round(st["ms_f"] / steps, 4), "ms_x": round(x_ms, 4), "tiles": c.tiles()}
+        c.close()
+        log(f"[bench] large N {prec}: {out[prec]}")
+    del x
+    torch.cuda.empty_cache()
+    out["int8_speedup_vs_fp32"] = round(out["int8"]["antenna_msps"] / out["fp32"]["antenna_msps"], 3)
+    return out
+
+
+def batch(corr, torch, metrics, steps, warmup):
+    """12 uneven jobs, (N, FFT size) drawn from the paper-scale set, 16384
+    spectra each, rho ~ U[0, 0.1]: one persistent launch replayed from a HIP
+    graph, all-int8 and all-fp32."""
+    import synth
+    recipes = synth.batch_jobs(12, seed=3)
+    S = 16384
+    xs = [synth.packed(r, 0, S, device="cuda").contiguous() for r in recipes]
+    a_s = sum(metrics.antenna_samples(r.N, r.two_k, S) for r in recipes)
+    out = {"workload": "12 jobs, (N, 2K) drawn from " + ", ".join(f"({n},{k})" for n, k in synth.BATCH_SHAPES)
+           + f", {S} spectra each", "jobs": [[r.N, r.two_k] for r in recipes]}
+    for prec in ("fp32", "int8"):
+        b = corr.Batch([(r.N, r.K, S, prec) for r in recipes], tiles="auto")
+        for _ in range(warmup):
+            b.process(xs)
+            for j in range(len(recipes)):
+                b.read_cps_raw(j)
+        times = []
+        for _ in range(steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            b.process(xs)
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+            for j in range(len(recipes)):
+                b.read_cps_raw(j)
+        ms = sorted(times)[len(times) // 2]
+        out[prec] = {"antenna_msps": round(a_s / (ms * 1e-3) / 1e6, 1), "ms_per_batch": round(ms, 4)}
+        b.close()
+        log(f"[bench] batch {prec}: {out[prec]}")
+    del xs
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(inputs_cpu_sample, S_sample):
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -122,6 +218,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-spectra", type=int, default=8192)
     ap.add_argument("--forms", default="fp32,fp16,int8")
+    ap.add_argument("--no-extra", action="store_true", help="skip the large-N and batch workloads")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device copy (scale reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -133,6 +232,13 @@ def main():
     from paper_1102_0148_amd import metrics
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)          # reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        del src, dst
     inputs = make_inputs("cuda")
     torch.cuda.synchronize()
 
@@ -175,17 +281,19 @@ def main():
         per_launch_ms = st["x"] / max(1, launches["x"])
         flops = metrics.x_ops(N_ANT, K, chunk)
         achieved = flops / (per_launch_ms * 1e-3) / 1e12
+        t = measured_traffic("xstage_kernel<0, 3, true>", chunk)
         roof = {"kernel": "xstage_kernel (fp32 MFMA, Hermitian rank-T update)", "bound": "mfma",
                 "achieved": round(achieved, 2), "peak": PEAK["fp32_tflops"], "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK["fp32_tflops"], 4), "traffic": None,
+                "frac": round(achieved / PEAK["fp32_tflops"], 4), "traffic": t,
                 "per_launch": {"useful_flops": flops, "avg_ms": round(per_launch_ms, 4)}}
     else:
         per_launch_ms = st["f"] / max(1, launches["f"])
         nbytes = metrics.antenna_samples(N_ANT, TWO_K, chunk) * (0.5 + 4.0)
         achieved = nbytes / (per_launch_ms * 1e-3) / 1e9
+        t = measured_traffic("fstage_kernel<256, 0, 8, false>", chunk)
         roof = {"kernel": "fstage_kernel (unpack + FFT + corner turn, fp32 records)", "bound": "hbm",
                 "achieved": round(achieved, 1), "peak": PEAK["hbm_gbs"], "unit": "GB/s",
-                "frac": round(achieved / PEAK["hbm_gbs"], 4), "traffic": None,
+                "frac": round(achieved / PEAK["hbm_gbs"], 4), "traffic": t,
                 "per_launch": {"algorithmic_bytes": nbytes, "avg_ms": round(per_launch_ms, 4)}}
 
     out = {
@@ -210,9 +318,16 @@ def main():
         "forms": forms,
         "roofline": roof,
     }
+    if not args.no_extra:
+        del inputs
+        torch.cuda.empty_cache()
+        out["large_n"] = large_n(corr, torch, metrics, max(2, args.steps // 3), 1)
+        out["batch"] = batch(corr, torch, metrics, max(3, args.steps // 3), 1)
     if not args.no_cpu_baseline:
         import numpy as np
-        sample = inputs[0][:args.cpu_spectra].cpu().numpy()
+        import synth
+        recipe = synth.recipe_plain(N=N_ANT, two_k=TWO_K, rho=0.05, seed=1)
+        sample = synth.packed(recipe, 0, args.cpu_spectra, device="cuda").cpu().numpy()
         out["cpu_baseline"] = cpu_baseline(sample, args.cpu_spectra)
     print(json.dumps(out))
 

@@ -239,7 +239,9 @@ def n_baselines(N: int) -> int:
 class Correlator:
     """One correlation (N antennas, K channels, n_spectra per integration)."""
 
-    def __init__(self, N: int, K: int, n_spectra: int, precision="fp32", tiles: Optional[dict] = None):
+    def __init__(self, N: int, K: int, n_spectra: int, precision="fp32", tiles=None):
+        """tiles: None (library defaults), "auto" (the autotuner's table,
+        defaults where it has no entry) or a dict of corr_tiles fields."""
         self.N, self.K, self.S = N, K, n_spectra
         self.nb = n_baselines(N)
         self.h = corr_create(N, K, n_spectra)
@@ -247,6 +249,11 @@ class Correlator:
             mode = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
             corr_set_precision(self.h, mode)
             self.precision = mode
+            if isinstance(tiles, str) and tiles == "auto":
+                from . import tune
+                name = {v: k for k, v in PRECISIONS.items()}[mode]
+                found = tune.lookup(N, K, n_spectra, name)
+                tiles = {k: found[k] for k in ("chunk_spectra", "x_splits", "f_group")} if found else None
             if tiles:
                 corr_set_tiles(self.h, **tiles)
         except Exception:
@@ -374,10 +381,18 @@ class Batch:
     replayed from a captured HIP graph.  jobs: list of (N, K, n_spectra,
     precision); tiles: optional {job index: {"x_splits": s}}."""
 
-    def __init__(self, jobs, tiles: Optional[dict] = None):
+    def __init__(self, jobs, tiles=None):
         self.jobs = [(int(N), int(K), int(S), PRECISIONS[p] if isinstance(p, str) else int(p))
                      for (N, K, S, p) in jobs]
         self.h = corr_batch_create(self.jobs)
+        if isinstance(tiles, str) and tiles == "auto":
+            from . import tune
+            names = {v: k for k, v in PRECISIONS.items()}
+            tiles = {}
+            for j, (N, K, S, p) in enumerate(self.jobs):
+                found = tune.lookup(N, K, S, names[p], batch=True)
+                if found:
+                    tiles[j] = {"x_splits": found["x_splits"]}
         try:
             for j, t in (tiles or {}).items():
                 corr_batch_set_tiles(self.h, j, **t)

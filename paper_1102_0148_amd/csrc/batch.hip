@@ -72,8 +72,11 @@ __device__ __forceinline__ void x_dispatch(const XArgs &xa, int rb, bool diag, i
     }
 }
 
-__device__ __forceinline__ unsigned load_acquire(unsigned *p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+// Coherent read of a counter without an acquire: the caller spins on this and
+// acquires once afterwards (an acquire per iteration would invalidate the L2
+// that the rest of the XCD is working out of).
+__device__ __forceinline__ unsigned load_relaxed(unsigned *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __global__ __launch_bounds__(256, 2) void batch_kernel(const BJob *jobs, const uint8_t *const *in_ptrs,
@@ -92,16 +95,17 @@ __global__ __launch_bounds__(256, 2) void batch_kernel(const BJob *jobs, const u
         if (it.wait >= 0) {
             if (threadIdx.x == 0) {
                 unsigned spins = 0;
-                while (load_acquire(&ctr[it.wait]) < (unsigned)it.wait_val) {
+                while (load_relaxed(&ctr[it.wait]) < (unsigned)it.wait_val) {
                     if (++spins > kBatchSpinLimit) {
                         atomicOr(err, 1u);
                         break;
                     }
                     __builtin_amdgcn_s_sleep(8);
                 }
+                // the producers' writes become visible to this workgroup
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
             __syncthreads();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         const BJob &j = jobs[it.job];
         switch (it.type) {
@@ -155,8 +159,9 @@ __global__ __launch_bounds__(256, 2) void batch_kernel(const BJob *jobs, const u
                 break;
             }
         }
-        // publish this item's writes, then count it
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        // publish this item's writes (every wave's, through the barrier and
+        // one agent-scope release), then count it
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __syncthreads();
         if (threadIdx.x == 0 && it.sig >= 0) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");

@@ -117,7 +117,7 @@ struct BItem {
 constexpr int kBatchCounters = 5;  // per job: power, scales, F, X, dump
 
 // Items per tile range, elements per scale / dump item.
-constexpr int kBatchTilesPerItem = 4;
+constexpr int kBatchTilesPerItem = 16;
 constexpr int kBatchElemsPerItem = 2048;
 // spin limit of a dependency wait (about a second); past it the kernel
 // records an error and goes on, so every wave always exits

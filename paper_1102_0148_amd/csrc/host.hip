@@ -694,7 +694,8 @@ int batch_build(corr_ctx *b) {
     HIP_TRY(hipSetDevice(b->device), "hipSetDevice");
     const int nj = (int)b->jobs.size();
     std::vector<BJob> bj(nj);
-    std::vector<BItem> power, scales, fitems, xitems, dumps;
+    std::vector<BItem> power, scales;
+    std::vector<std::vector<BItem>> fitems(nj), xitems(nj), dumps(nj);
     int lds = 0;
     for (int j = 0; j < nj; ++j) {
         corr_ctx *h = b->jobs[j];
@@ -768,17 +769,26 @@ int batch_build(corr_ctx *b) {
         }
         int n_f = 0;
         for (int t = 0; t < d.f.ntiles; t += kBatchTilesPerItem, ++n_f)
-            fitems.push_back(BItem{BI_F, j, t, std::min(t + kBatchTilesPerItem, d.f.ntiles),
+            fitems[j].push_back(BItem{BI_F, j, t, std::min(t + kBatchTilesPerItem, d.f.ntiles),
                                    h->prec == kINT8 ? c0 + 1 : -1, n_scales, c0 + 2, 0});
         const int wd = (h->n_diag * h->K * xa.nsplit + 3) / 4, wo = (h->n_off * h->K * xa.nsplit + 3) / 4;
-        for (int x = 0; x < wd; ++x) xitems.push_back(BItem{BI_XD, j, x, 0, c0 + 2, n_f, c0 + 3, 0});
-        for (int x = 0; x < wo; ++x) xitems.push_back(BItem{BI_XO, j, x, 0, c0 + 2, n_f, c0 + 3, 0});
+        for (int x = 0; x < wd; ++x) xitems[j].push_back(BItem{BI_XD, j, x, 0, c0 + 2, n_f, c0 + 3, 0});
+        for (int x = 0; x < wo; ++x) xitems[j].push_back(BItem{BI_XO, j, x, 0, c0 + 2, n_f, c0 + 3, 0});
         for (int e = 0; e < d.n_acc; e += kBatchElemsPerItem)
-            dumps.push_back(BItem{BI_DUMP, j, e, std::min(e + kBatchElemsPerItem, d.n_acc), c0 + 3, wd + wo,
-                                  c0 + 4, 0});
+            dumps[j].push_back(BItem{BI_DUMP, j, e, std::min(e + kBatchElemsPerItem, d.n_acc), c0 + 3,
+                                     wd + wo, c0 + 4, 0});
     }
+    // calibration first, then F of job j, X of job j-1 and dumps of job j-2:
+    // the MFMA-heavy X-stage of one job overlaps the F-stage of the next, and
+    // a job's X items are taken only once its F items have been handed out
     std::vector<BItem> items;
-    for (auto *v : {&power, &scales, &fitems, &xitems, &dumps}) items.insert(items.end(), v->begin(), v->end());
+    items.insert(items.end(), power.begin(), power.end());
+    items.insert(items.end(), scales.begin(), scales.end());
+    for (int j = 0; j < nj + 2; ++j) {
+        if (j < nj) items.insert(items.end(), fitems[j].begin(), fitems[j].end());
+        if (j >= 1 && j - 1 < nj) items.insert(items.end(), xitems[j - 1].begin(), xitems[j - 1].end());
+        if (j >= 2) items.insert(items.end(), dumps[j - 2].begin(), dumps[j - 2].end());
+    }
     b->n_items = (int)items.size();
     b->n_ctr = 2 + nj * kBatchCounters;
     b->b_lds = lds;

@@ -1,0 +1,180 @@
+"""Autotuner for the correlator's tile choices.
+
+For one job shape (N antennas, K channels, n_spectra, precision) it times
+every candidate (chunk_spectra, x_splits, f_group) with the library's own
+stage timers (HIP events on the launch stream) over a few integrations of
+synthetic input, and keeps the fastest.  Batch jobs (one chunk per job, the
+F-stage group fixed by the batch kernel) are tuned over x_splits in a batch of
+their own.  Results go to a JSON table keyed by (arch, N, K, n_spectra,
+precision[, batch]) that Correlator(tiles="auto") and Batch(tiles="auto") read.
+
+Run on the GPU:  python -m paper_1102_0148_amd.tune --out tuned.json [shapes]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+from typing import Dict, Iterable, List, Optional, Tuple
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TABLE = os.path.join(HERE, "tuned_tiles.json")
+ARCH = "gfx950"
+LDS_LIMIT = 160 * 1024
+SPLITS = (4, 8, 12, 16, 24, 32, 48, 64)
+MAX_SPECTRA_PER_PARTIAL = 2048   # float partials stay short (accuracy)
+
+
+def record_times(prec: str) -> int:
+    return {"fp32": 2, "fp16": 4, "int8": 8}[prec]
+
+
+def f_lds_bytes(K: int, prec: str, group: int) -> int:
+    L = K // 16
+    fpr = 256 // L
+    slot = K + K // 16 + 1
+    return record_times(prec) * group * slot * 8 + fpr * K
+
+
+def key(N: int, K: int, S: int, prec: str, batch: bool = False) -> str:
+    return f"{ARCH}:N={N}:K={K}:S={S}:{prec}" + (":batch" if batch else "")
+
+
+def candidates(N: int, K: int, S: int, prec: str) -> List[dict]:
+    """Every tile choice the tuner considers for a single job."""
+    whole = (S + 63) // 64 * 64
+    chunks = sorted({c for c in (whole, whole // 2, whole // 4, 16384, 8192) if 1024 <= c <= whole and c % 64 == 0}
+                    | {whole})
+    groups = [g for g in (1, 2, 4, 8, 16) if f_lds_bytes(K, prec, g) <= LDS_LIMIT]
+    out = []
+    for chunk in chunks:
+        for s in SPLITS:
+            if prec != "int8" and chunk / s > MAX_SPECTRA_PER_PARTIAL:
+                continue
+            for g in groups:
+                out.append({"chunk_spectra": chunk, "x_splits": s, "f_group": g})
+    return out
+
+
+def load_table(path: str = TABLE) -> Dict[str, dict]:
+    if os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    return {}
+
+
+def lookup(N: int, K: int, S: int, prec: str, batch: bool = False, path: str = TABLE) -> Optional[dict]:
+    return load_table(path).get(key(N, K, S, prec, batch))
+
+
+def _time_single(corr, torch, N, K, S, prec, tiles, x, reps=3, warm=1) -> float:
+    c = corr.Correlator(N, K, S, precision=prec, tiles=tiles)
+    dst = torch.empty(c.nb * K * 2, dtype=torch.float64, device="cuda")
+    try:
+        for _ in range(warm):
+            c.process(x)
+            c.read_cps_async(dst)
+        c.enable_timing(True)
+        for _ in range(reps):
+            c.process(x)
+            c.read_cps_async(dst)
+        st = c.stats()
+        return (st["ms_f"] + st["ms_x"] + st["ms_dump"] + st["ms_calib"]) / reps
+    finally:
+        c.close()
+        del dst
+        torch.cuda.empty_cache()
+
+
+def tune_single(N: int, K: int, S: int, prec: str, log=print) -> Tuple[dict, float, List[Tuple[dict, float]]]:
+    import torch
+    import paper_1102_0148_amd as corr
+    import synth
+    x = synth.packed(synth.recipe_plain(N=N, two_k=2 * K, seed=11), 0, S, device="cuda").contiguous()
+    results = []
+    # stage 1: chunk and splits at the default group; stage 2: groups at the best
+    base_group = None
+    cands = candidates(N, K, S, prec)
+    default_groups = {c["f_group"] for c in cands}
+    fpr = 256 // (K // 16)
+    dg = max(1, fpr // record_times(prec))
+    base_group = dg if dg in default_groups else min(default_groups)
+    for t in [c for c in cands if c["f_group"] == base_group]:
+        ms = _time_single(corr, torch, N, K, S, prec, t, x)
+        results.append((t, ms))
+        log(f"  {prec} N={N} K={K} {t} {ms:.4f} ms")
+    best = min(results, key=lambda r: r[1])[0]
+    for t in [c for c in cands if c["chunk_spectra"] == best["chunk_spectra"] and
+              c["x_splits"] == best["x_splits"] and c["f_group"] != base_group]:
+        ms = _time_single(corr, torch, N, K, S, prec, t, x)
+        results.append((t, ms))
+        log(f"  {prec} N={N} K={K} {t} {ms:.4f} ms")
+    best, best_ms = min(results, key=lambda r: r[1])
+    return best, best_ms, results
+
+
+def tune_batch_job(N: int, K: int, S: int, prec: str, log=print) -> Tuple[dict, float]:
+    import torch
+    import paper_1102_0148_amd as corr
+    import synth
+    x = synth.packed(synth.recipe_plain(N=N, two_k=2 * K, seed=12), 0, S, device="cuda").contiguous()
+    best = None
+    for s in SPLITS:
+        if prec != "int8" and S / s > MAX_SPECTRA_PER_PARTIAL:
+            continue
+        b = corr.Batch([(N, K, S, prec)], tiles={0: {"x_splits": s}})
+        try:
+            b.process([x])
+            b.read_cps_raw(0)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(3):
+                b.process([x])
+                b.read_cps_raw(0)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 3
+        finally:
+            b.close()
+        log(f"  batch {prec} N={N} K={K} x_splits={s} {ms:.4f} ms")
+        if best is None or ms < best[1]:
+            best = ({"x_splits": s}, ms)
+    return best
+
+
+def main(argv: Optional[Iterable[str]] = None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=TABLE)
+    ap.add_argument("--single", default="44:256:65536:fp32,44:256:65536:fp16,44:256:65536:int8,"
+                                        "256:512:16384:fp32,256:512:16384:int8")
+    ap.add_argument("--batch", default="8:128:16384,12:256:16384,16:512:16384,24:256:16384,"
+                                       "32:1024:16384,44:256:16384,64:512:16384,96:256:16384")
+    ap.add_argument("--batch-precisions", default="int8,fp32")
+    args = ap.parse_args(argv)
+    sys.path.insert(0, os.path.dirname(HERE))
+    import torch
+    torch.cuda.set_device(0)
+    table = load_table(args.out)
+    for item in filter(None, args.single.split(",")):
+        N, K, S, prec = item.split(":")
+        N, K, S = int(N), int(K), int(S)
+        best, ms, _ = tune_single(N, K, S, prec)
+        table[key(N, K, S, prec)] = dict(best, ms=round(ms, 4))
+        print(f"best {key(N, K, S, prec)}: {table[key(N, K, S, prec)]}", flush=True)
+        with open(args.out, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+    for item in filter(None, args.batch.split(",")):
+        N, K, S = (int(v) for v in item.split(":"))
+        for prec in args.batch_precisions.split(","):
+            best, ms = tune_batch_job(N, K, S, prec)
+            table[key(N, K, S, prec, batch=True)] = dict(best, ms=round(ms, 4))
+            print(f"best {key(N, K, S, prec, True)}: {table[key(N, K, S, prec, True)]}", flush=True)
+            with open(args.out, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -338,3 +338,25 @@ def test_state_errors():
 
 def round_up(x, m):
     return (x + m - 1) // m * m
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "int8"])
+def test_every_autotuner_candidate_passes_parity(prec):
+    """Each tile choice the autotuner may pick: float forms within tolerance
+    of the oracle, int8 identical to every other candidate."""
+    from paper_1102_0148_amd import tune
+    N, K, S = 44, 256, 300
+    packed = _packed(synth.recipe_plain(N=N, two_k=2 * K, seed=21), S)
+    ref = oracle.correlate(packed.cpu().numpy(), S, N, K)
+    cands = tune.candidates(N, K, S, prec)
+    assert len(cands) >= 20
+    first = None
+    for t in cands:
+        _, raw = run(N, K, S, packed, precision=corr.PRECISIONS[prec], tiles=t)
+        if prec == "int8":
+            if first is None:
+                first = raw
+            else:
+                np.testing.assert_array_equal(raw, first)
+        else:
+            assert coef_error(raw_to_complex(raw), ref, N) <= TOL[corr.PRECISIONS[prec]], t
