@@ -28,10 +28,7 @@ __device__ __noinline__ void f_range(const FArgs &fa, int t0, int t1, char *lds)
     using Sh = FShape<M, PREC, GA, false>;
     float2 *zbuf = reinterpret_cast<float2 *>(lds);
     uint32_t *bbuf = reinterpret_cast<uint32_t *>(lds + (Sh::NF * Sh::SLOT * 8 + 15) / 16 * 16);
-    for (int t = t0; t < t1; ++t) {
-        f_tile<M, PREC, GA>(fa, t, zbuf, bbuf);
-        __syncthreads();  // zbuf is rewritten by the next tile
-    }
+    f_tiles<M, PREC, GA>(fa, t0, 1, t1, zbuf, bbuf);
 }
 
 template <int M>

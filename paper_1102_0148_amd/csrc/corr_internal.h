@@ -47,7 +47,7 @@ struct FArgs {
     uint4 *spec;              // records, index rec_index(c, tq, a, M, a_pad)
     float *power;             // power mode: partial sums [nwg_per_group][a_pad][M]
     const float *scales;      // int8: [N][M]
-    const float2 *tw;         // W_M^j (j < M), then W_2M^q (q < M/2)
+    const float2 *tw;         // W_M^j (j < M), W_2M^q (q < M/2), then M zero bytes
     unsigned long long *sat;  // int8 saturation counter
     int N, a_pad, S;          // S = spectra in this chunk
     int ntq;                  // power mode: time tiles in the window
@@ -57,8 +57,9 @@ struct FArgs {
 };
 
 // Launch the F-stage for complex length M = K (channels).  mode: 0 = spectra
-// records in precision `prec`; 1 = power sums over the calibration window
-// (records not written).  Returns hipSuccess or the launch error.
+// records in precision `prec`, over as many persistent workgroups as stay
+// resident (`grid` ignored); 1 = power sums over the calibration window
+// (records not written), `grid` blocks.  Returns hipSuccess or the error.
 hipError_t launch_fstage(int M, int prec, int ga, int power_mode, const FArgs &a, int grid,
                          hipStream_t st);
 int fstage_lds_bytes(int M, int prec, int ga);

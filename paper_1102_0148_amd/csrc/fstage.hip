@@ -11,13 +11,15 @@ __global__ __launch_bounds__(kThreads) void fstage_kernel(FArgs args) {
     __shared__ float2 zbuf[Sh::NF * Sh::SLOT];
     __shared__ __attribute__((aligned(16))) uint32_t bbuf[Sh::FPR * (M / 4)];
     if constexpr (!POWER) {
-        // one tile per workgroup; workgroups b, b+8, b+16, ... share an XCD
-        // (round-robin dispatch), so they take consecutive antenna groups of
-        // one time record and their partial lines meet in one L2
+        // persistent workgroups; workgroup b runs on XCD b % 8 (round-robin
+        // dispatch), and the tiles of XCD x are the range [x t8, (x+1) t8),
+        // dealt round-robin to its workgroups: tiles in flight on one XCD are
+        // neighbours (consecutive antenna groups of nearby time records) whose
+        // partial lines meet in one L2
+        const int nw8 = gridDim.x / 8;
         const int t8 = (args.ntiles + 7) / 8;
-        const int tile = (blockIdx.x % 8) * t8 + blockIdx.x / 8;
-        if (tile >= args.ntiles) return;
-        f_tile<M, PREC, GA>(args, tile, zbuf, bbuf);
+        const int lo = (blockIdx.x % 8) * t8, hi = min(lo + t8, args.ntiles);
+        f_tiles<M, PREC, GA>(args, lo + blockIdx.x / 8, nw8, hi, zbuf, bbuf);
     } else {
         f_power_block<M>(args, blockIdx.x, zbuf, bbuf);
     }
@@ -28,6 +30,19 @@ hipError_t launch_one(const FArgs &a, int grid, hipStream_t st) {
     if constexpr (FShape<M, PREC, GA, POWER>::LDS > 160 * 1024) {
         return hipErrorInvalidValue;
     } else {
+        if (!POWER) {
+            // as many workgroups (a multiple of 8) as stay resident, at most one
+            // per tile
+            int per_cu = 0, dev = 0, cus = 0;
+            hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, fstage_kernel<M, PREC, GA, POWER>, kThreads, 0);
+            if (e == hipSuccess) e = hipGetDevice(&dev);
+            if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+            if (e != hipSuccess) return e;
+            const int cap = per_cu * cus / 8 > 0 ? per_cu * cus / 8 : 1;
+            const int need = (a.ntiles + 7) / 8;
+            grid = 8 * (need < cap ? need : cap);
+        }
         hipLaunchKernelGGL((fstage_kernel<M, PREC, GA, POWER>), dim3(grid), dim3(kThreads), 0, st, a);
         return hipGetLastError();
     }

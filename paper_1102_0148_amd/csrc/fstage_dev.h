@@ -118,9 +118,10 @@ __device__ __forceinline__ int pad(int e) { return e + (e >> 4); }
 
 // Stockham pass of radix R (p = product of the radices before it), in place
 // in one transform's LDS slot.  Butterfly i reads z[i + r M/R], multiplies by
-// W_{pR}^{r k} (k = i mod p), and writes z[(i - k) R + k + r p].
+// W_{pR}^{r k} (k = i mod p), and writes z[(i - k) R + k + r p].  The lane's
+// twiddles come in registers, tw[m (R-1) + r - 1] for its butterfly m.
 template <int M, int R>
-__device__ __forceinline__ void fft_pass(float2 *z, int j, int p, const float2 *twM) {
+__device__ __forceinline__ void fft_pass(float2 *z, int j, int p, const float2 *tw) {
     constexpr int L = M / 16;
     constexpr int T = M / R;
     constexpr int NBF = 16 / R;
@@ -136,15 +137,45 @@ __device__ __forceinline__ void fft_pass(float2 *z, int j, int p, const float2 *
     for (int m = 0; m < NBF; ++m) {
         const int i = j + L * m;
         const int k = i & (p - 1);
-        const int step = k * (M / (p * R));
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[m * R + r] = cmul(v[m * R + r], twM[(r * step) & (M - 1)]);
+        for (int r = 1; r < R; ++r) v[m * R + r] = cmul(v[m * R + r], tw[m * (R - 1) + r - 1]);
         dft_r<R>(&v[m * R]);
         const int base = (i - k) * R + k;
 #pragma unroll
         for (int r = 0; r < R; ++r) z[pad(base + r * p)] = v[m * R + r];
     }
 }
+
+// The twiddles lane j needs in a pass of radix R after p points: W_M^(r k
+// M/(pR)) for each of its butterflies m (k = (j + L m) mod p) and r = 1..R-1.
+template <int M, int R>
+__device__ __forceinline__ void pass_twiddles(int j, int p, const float2 *twM, float2 *out) {
+    constexpr int L = M / 16;
+#pragma unroll
+    for (int m = 0; m < 16 / R; ++m) {
+        const int k = (j + L * m) & (p - 1);
+        const int step = k * (M / (p * R));
+#pragma unroll
+        for (int r = 1; r < R; ++r) out[m * (R - 1) + r - 1] = twM[(r * step) & (M - 1)];
+    }
+}
+
+// A lane's twiddles for every pass after the first: radix 16 (8 for M = 128)
+// after 16 points, then radix 2 (M = 512) or 4 (M = 1024) after 256.  They
+// depend only on the lane, so a workgroup loads them once.
+template <int M>
+struct PassTw {
+    static constexpr int R2 = M == 128 ? 8 : 16;
+    static constexpr int R3 = M == 512 ? 2 : (M == 1024 ? 4 : 1);
+    static constexpr int N2 = (16 / R2) * (R2 - 1);
+    static constexpr int N3 = R3 > 1 ? (16 / R3) * (R3 - 1) : 1;
+    float2 w2[N2];
+    float2 w3[N3];
+    __device__ __forceinline__ void load(int j, const float2 *twM) {
+        pass_twiddles<M, R2>(j, 16, twM, w2);
+        if constexpr (R3 > 1) pass_twiddles<M, R3>(j, 256, twM, w3);
+    }
+};
 
 // Signed nibble at bit offset `off` of w.
 __device__ __forceinline__ float nib(uint32_t w, int off) {
@@ -184,10 +215,10 @@ __device__ __forceinline__ uint4 make_record(const float *re, const float *im, f
     return out;
 }
 
-// Real-input bins q and K-q (q = 0: bins 0 and K/2) from a transform slot.
+// Real-input bins q and K-q (q = 0: bins 0 and K/2) from a transform slot;
+// w = W_2K^q.
 template <int M>
-__device__ __forceinline__ void real_bins(const float2 *zs, int q, const float2 *tw2, float2 &xlo,
-                                          float2 &xhi) {
+__device__ __forceinline__ void real_bins(const float2 *zs, int q, float2 w, float2 &xlo, float2 &xhi) {
     if (q == 0) {
         const float2 z0 = zs[0], zh = zs[pad(M / 2)];
         xlo = make_float2(z0.x + z0.y, 0.0f);
@@ -196,7 +227,7 @@ __device__ __forceinline__ void real_bins(const float2 *zs, int q, const float2 
         const float2 z0 = zs[pad(q)], z1 = zs[pad(M - q)];
         const float2 A = make_float2(z0.x + z1.x, z0.y - z1.y);
         const float2 B = make_float2(z0.x - z1.x, z0.y + z1.y);
-        const float2 C = cmul(B, tw2[q]);
+        const float2 C = cmul(B, w);
         xlo = make_float2(0.5f * (A.x + C.y), 0.5f * (A.y - C.x));
         xhi = make_float2(0.5f * (A.x - C.y), 0.5f * (-A.y - C.x));
     }
@@ -215,28 +246,44 @@ struct FShape {
     static constexpr int LDS = NF * SLOT * 8 + FPR * M;
 };
 
-// Transform the NF blocks of tile (tq, g) into zbuf slots (ts * GA + ga).
+// Frames of tile (tq, g): transform slot fi = r FPR + fs of round r takes the
+// 16 bytes j of block (spectrum tq TS + fi / GA, antenna g GA + fi % GA);
+// blocks past the chunk or past N are read from the zero bytes after the
+// twiddle table.  Every lane issues its load and nothing selects on the data
+// afterwards, so no branch or select ties a later wait to this load.
 template <int M, int GA, int TS, int NF, int ROUNDS>
-__device__ __forceinline__ void tile_ffts(const FArgs &args, int tq, int g, float2 *zbuf, uint32_t *bbuf,
-                                          const float2 *twM) {
+__device__ __forceinline__ void load_tile(const FArgs &args, int tq, int g, u32x4 (&raw)[ROUNDS]) {
+    constexpr int L = M / 16, FPR = kThreads / L;
+    const int fs = threadIdx.x / L, j = threadIdx.x % L;
+    const uint8_t *zeros = reinterpret_cast<const uint8_t *>(args.tw + M + M / 2);
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+        const int fi = r * FPR + fs;
+        const int s = tq * TS + fi / GA, a = g * GA + fi % GA;
+        const bool ok = fi < NF && s < args.S && a < args.N;
+        const uint8_t *src = ok ? args.in + ((int64_t)s * args.N + a) * M : zeros;
+        // frames are read once: stream them past the caches
+        raw[r] = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(src + 16 * j));
+    }
+}
+
+// Transform the NF blocks of a tile, loaded by load_tile, into zbuf slots
+// (ts * GA + ga).
+template <int M, int NF, int ROUNDS>
+__device__ __forceinline__ void tile_ffts(const u32x4 (&raw)[ROUNDS], float2 *zbuf, uint32_t *bbuf,
+                                          const PassTw<M> &tw) {
     constexpr int L = M / 16, FPR = kThreads / L, SLOT = M + M / 16 + 1;
     const int fs = threadIdx.x / L, j = threadIdx.x % L;
     uint32_t *bb = bbuf + fs * (M / 4);
-#pragma unroll 1
+#pragma unroll
     for (int r = 0; r < ROUNDS; ++r) {
         const int fi = r * FPR + fs;
-        if (ROUNDS * FPR > NF && fi >= NF) break;  // idle transform slots of the last round
-        const int ts = fi / GA, ga = fi % GA;
-        const int s = tq * TS + ts, a = g * GA + ga;
+        if (NF < FPR && fi >= NF) break;  // idle transform slots (one round only)
         float2 *z = zbuf + fi * SLOT;
-        u32x4 raw = {0u, 0u, 0u, 0u};
-        if (s < args.S && a < args.N)  // frames are read once: stream them past the caches
-            raw = __builtin_nontemporal_load(
-                reinterpret_cast<const u32x4 *>(args.in + ((int64_t)s * args.N + a) * M + 16 * j));
         // dword d of the block goes to (d mod L/4)*16 + d div L/4, so the 16
         // dwords pass 1 needs in a lane are contiguous
         {
-            const uint32_t w[4] = {raw[0], raw[1], raw[2], raw[3]};
+            const uint32_t w[4] = {raw[r][0], raw[r][1], raw[r][2], raw[r][3]};
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const int d = 4 * j + c;
@@ -264,61 +311,89 @@ __device__ __forceinline__ void tile_ffts(const FArgs &args, int tq, int g, floa
             for (int q = 0; q < 16; ++q) z[pad(16 * j + q)] = v[q];
         }
         wave_lds_sync();
-        if constexpr (M == 128) {
-            fft_pass<M, 8>(z, j, 16, twM);
-        } else {
-            fft_pass<M, 16>(z, j, 16, twM);
-            if constexpr (M == 512) {
-                wave_lds_sync();
-                fft_pass<M, 2>(z, j, 256, twM);
-            } else if constexpr (M == 1024) {
-                wave_lds_sync();
-                fft_pass<M, 4>(z, j, 256, twM);
-            }
+        fft_pass<M, PassTw<M>::R2>(z, j, 16, tw.w2);
+        if constexpr (PassTw<M>::R3 > 1) {
+            wave_lds_sync();
+            fft_pass<M, PassTw<M>::R3>(z, j, 256, tw.w3);
         }
         wave_lds_sync();
     }
 }
 
-// One tile (time record tq, antenna group g) of spectra records: TS spectra
-// of GA antennas transformed, turned into bins and written as records.  The
-// caller separates consecutive calls with a workgroup barrier.
+// Tiles t0, t0 + stride, ... below t1 of spectra records; tile = time record
+// tq * ngroups + antenna group g.  Each tile's TS spectra of GA antennas are
+// transformed, turned into bins and written as records.  The next tile's
+// frames are read while the current one is transformed, and the twiddles are
+// loaded once, so neither latency sits between a tile's stages.
 template <int M, int PREC, int GA>
-__device__ __forceinline__ void f_tile(const FArgs &args, int tile, float2 *zbuf, uint32_t *bbuf) {
+__device__ __forceinline__ void f_tiles(const FArgs &args, int t0, int stride, int t1, float2 *zbuf,
+                                        uint32_t *bbuf) {
     using Sh = FShape<M, PREC, GA, false>;
-    constexpr int TS = Sh::TS, SLOT = Sh::SLOT, NTASK = Sh::NTASK, TPT = Sh::TPT;
+    constexpr int TS = Sh::TS, SLOT = Sh::SLOT, NF = Sh::NF, ROUNDS = Sh::ROUNDS;
+    constexpr int NTASK = Sh::NTASK, TPT = Sh::TPT;
+    if (t0 >= t1) return;
     const int tid = threadIdx.x;
-    const float2 *twM = args.tw;
-    const float2 *tw2 = args.tw + M;
-    const int tq = tile / args.ngroups, g = tile % args.ngroups;
-    tile_ffts<M, GA, TS, Sh::NF, Sh::ROUNDS>(args, tq, g, zbuf, bbuf, twM);
-    __syncthreads();
-    unsigned nsat = 0;
+    PassTw<M> ptw;
+    ptw.load(tid % (M / 16), args.tw);
+    // W_2M^q of this thread's bin pairs (task t = bin pair q, antenna ga)
+    float2 bw[TPT];
 #pragma unroll
     for (int it = 0; it < TPT; ++it) {
         const int t = tid + it * kThreads;
-        if (NTASK % kThreads != 0 && t >= NTASK) break;
-        const int ga = t % GA, q = t / GA;
-        const int a = g * GA + ga;
-        float lr[TS], li[TS], hr[TS], hi[TS];
+        bw[it] = (NTASK % kThreads == 0 || t < NTASK) ? args.tw[M + t / GA] : make_float2(1.0f, 0.0f);
+    }
+    u32x4 raw[ROUNDS];
+    load_tile<M, GA, TS, NF, ROUNDS>(args, t0 / args.ngroups, t0 % args.ngroups, raw);
+    // Wait for the first frames here, before the loop: otherwise the wait at
+    // the loop head, which must also cover this path, is a wait for every
+    // memory operation, and each tile would wait for the previous tile's
+    // record stores to land.  (vmcnt(0), expcnt and lgkmcnt left alone.)
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    unsigned nsat = 0;
+    for (int tile = t0; tile < t1; tile += stride) {
+        const int tq = tile / args.ngroups, g = tile % args.ngroups;
+        float slo[TPT], shi[TPT];
 #pragma unroll
-        for (int ts = 0; ts < TS; ++ts) {
-            float2 xlo, xhi;
-            real_bins<M>(zbuf + (ts * GA + ga) * SLOT, q, tw2, xlo, xhi);
-            lr[ts] = xlo.x; li[ts] = xlo.y; hr[ts] = xhi.x; hi[ts] = xhi.y;
-        }
-        const int clo = q, chi = q == 0 ? M / 2 : M - q;
-        float slo = 1.0f, shi = 1.0f;
-        if constexpr (PREC == kINT8) {
-            if (a < args.N) {
-                slo = args.scales[(int64_t)a * M + clo];
-                shi = args.scales[(int64_t)a * M + chi];
+        for (int it = 0; it < TPT; ++it) {
+            slo[it] = shi[it] = 1.0f;
+            if constexpr (PREC == kINT8) {
+                // unconditional loads, as in load_tile; antennas past N have
+                // zero spectra and take antenna 0's scales
+                const int t = tid + it * kThreads;
+                const bool ok = (NTASK % kThreads == 0 || t < NTASK) && g * GA + t % GA < args.N;
+                const int a = ok ? g * GA + t % GA : 0, q = ok ? t / GA : 0;
+                slo[it] = args.scales[(int64_t)a * M + q];
+                shi[it] = args.scales[(int64_t)a * M + (q == 0 ? M / 2 : M - q)];
             }
         }
-        const uint4 rlo = make_record<PREC, TS>(lr, li, slo, nsat);
-        const uint4 rhi = make_record<PREC, TS>(hr, hi, shi, nsat);
-        args.spec[rec_index(clo, tq, a, M, args.a_pad)] = rlo;
-        args.spec[rec_index(chi, tq, a, M, args.a_pad)] = rhi;
+        u32x4 cur[ROUNDS];
+#pragma unroll
+        for (int r = 0; r < ROUNDS; ++r) cur[r] = raw[r];
+        // the last tile re-reads its own frames rather than branch around the load
+        const int nxt = tile + stride < t1 ? tile + stride : tile;
+        load_tile<M, GA, TS, NF, ROUNDS>(args, nxt / args.ngroups, nxt % args.ngroups, raw);
+        tile_ffts<M, NF, ROUNDS>(cur, zbuf, bbuf, ptw);
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < TPT; ++it) {
+            const int t = tid + it * kThreads;
+            if (NTASK % kThreads != 0 && t >= NTASK) break;
+            const int ga = t % GA, q = t / GA;
+            const int a = g * GA + ga;
+            float lr[TS], li[TS], hr[TS], hi[TS];
+#pragma unroll
+            for (int ts = 0; ts < TS; ++ts) {
+                float2 xlo, xhi;
+                real_bins<M>(zbuf + (ts * GA + ga) * SLOT, q, bw[it], xlo, xhi);
+                lr[ts] = xlo.x; li[ts] = xlo.y; hr[ts] = xhi.x; hi[ts] = xhi.y;
+            }
+            const int clo = q, chi = q == 0 ? M / 2 : M - q;
+            const uint4 rlo = make_record<PREC, TS>(lr, li, slo[it], nsat);
+            const uint4 rhi = make_record<PREC, TS>(hr, hi, shi[it], nsat);
+            args.spec[rec_index(clo, tq, a, M, args.a_pad)] = rlo;
+            args.spec[rec_index(chi, tq, a, M, args.a_pad)] = rhi;
+        }
+        __syncthreads();  // zbuf and bbuf are rewritten by the next tile
     }
     if constexpr (PREC == kINT8) {
         if (nsat) atomicAdd(args.sat, (unsigned long long)nsat);
@@ -332,20 +407,28 @@ template <int M>
 __device__ __forceinline__ void f_power_block(const FArgs &args, int blk, float2 *zbuf, uint32_t *bbuf) {
     constexpr int GA = power_group(M);
     using Sh = FShape<M, kFP32, GA, true>;
-    constexpr int TS = Sh::TS, SLOT = Sh::SLOT, NTASK = Sh::NTASK, TPT = Sh::TPT;
+    constexpr int TS = Sh::TS, SLOT = Sh::SLOT, NF = Sh::NF, ROUNDS = Sh::ROUNDS;
+    constexpr int NTASK = Sh::NTASK, TPT = Sh::TPT;
     const int tid = threadIdx.x;
-    const float2 *twM = args.tw;
-    const float2 *tw2 = args.tw + M;
     const int nblk_t = (args.ntq + args.tiles_per_wg - 1) / args.tiles_per_wg;
     const int pg = blk / nblk_t, pw = blk % nblk_t;
     if (pg >= args.ngroups) return;
     const int tile0 = pw * args.tiles_per_wg;
     const int tile1 = min(tile0 + args.tiles_per_wg, args.ntq);
+    PassTw<M> ptw;
+    ptw.load(tid % (M / 16), args.tw);
+    float2 bw[TPT];
     float plo[TPT], phi[TPT];
 #pragma unroll
-    for (int it = 0; it < TPT; ++it) plo[it] = phi[it] = 0.0f;
+    for (int it = 0; it < TPT; ++it) {
+        const int t = tid + it * kThreads;
+        bw[it] = (NTASK % kThreads == 0 || t < NTASK) ? args.tw[M + t / GA] : make_float2(1.0f, 0.0f);
+        plo[it] = phi[it] = 0.0f;
+    }
     for (int tq = tile0; tq < tile1; ++tq) {
-        tile_ffts<M, GA, TS, Sh::NF, Sh::ROUNDS>(args, tq, pg, zbuf, bbuf, twM);
+        u32x4 raw[ROUNDS];
+        load_tile<M, GA, TS, NF, ROUNDS>(args, tq, pg, raw);
+        tile_ffts<M, NF, ROUNDS>(raw, zbuf, bbuf, ptw);
         __syncthreads();
 #pragma unroll
         for (int it = 0; it < TPT; ++it) {
@@ -355,7 +438,7 @@ __device__ __forceinline__ void f_power_block(const FArgs &args, int blk, float2
 #pragma unroll
             for (int ts = 0; ts < TS; ++ts) {
                 float2 xlo, xhi;
-                real_bins<M>(zbuf + (ts * GA + ga) * SLOT, q, tw2, xlo, xhi);
+                real_bins<M>(zbuf + (ts * GA + ga) * SLOT, q, bw[it], xlo, xhi);
                 plo[it] += fmaf(xlo.x, xlo.x, xlo.y * xlo.y);
                 phi[it] += fmaf(xhi.x, xhi.x, xhi.y * xhi.y);
             }

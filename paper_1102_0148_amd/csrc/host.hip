@@ -344,9 +344,8 @@ int process_one(corr_ctx *h, const uint8_t *in, hipStream_t st) {
         fa.ntq = h->ntq_buf;
         fa.ngroups = ngroups;
         fa.ntiles = ntq_used * ngroups;
-        const int grid = 8 * ((fa.ntiles + 7) / 8);  // one tile per workgroup
         timer_begin(h, 1, st);
-        HIP_TRY(launch_fstage(h->K, h->prec, ga, 0, fa, grid, st), "F-stage launch");
+        HIP_TRY(launch_fstage(h->K, h->prec, ga, 0, fa, 0, st), "F-stage launch");
         timer_end(h, st);
         h->launches_f++;
         int rc = launch_x_and_dump(h, h->spec, h->ntq_buf, ntq_used / 4, st);
@@ -444,8 +443,9 @@ corr_ctx *create_ctx(int N, int K, int S) {
     hipError_t e = hipGetDevice(&h->device);
     if (e != hipSuccess) return bail(e, "hipGetDevice");
     if ((e = set_regions(h, h->rb)) != hipSuccess) return bail(e, "regions");
-    // twiddles: W_K^j, j < K, then W_2K^q, q < K/2
-    std::vector<float2> tw((size_t)K + K / 2);
+    // twiddles: W_K^j, j < K, then W_2K^q, q < K/2, then K bytes of zeros
+    // (the F-stage reads its absent blocks from there)
+    std::vector<float2> tw((size_t)K + K / 2 + K / 8, make_float2(0.0f, 0.0f));
     for (int j = 0; j < K; ++j) tw[j] = twiddle(j, K);
     for (int q = 0; q < K / 2; ++q) tw[K + q] = twiddle(q, 2 * K);
     if ((e = hipMalloc(&h->tw, tw.size() * sizeof(float2))) != hipSuccess) return bail(e, "hipMalloc(twiddles)");
