@@ -7,8 +7,9 @@
 // whose inputs come from earlier items waits on a per-job counter, and a
 // finished item increments its counter.  An item only ever waits for items
 // with smaller tickets, which running workgroups already hold, so the queue
-// always drains.  Counters are read with agent-scope acquire and bumped after
-// an agent-scope release, which carries the data across the XCDs' L2 caches.
+// always drains.  Counters are bumped with an agent-scope release and read
+// with an agent-scope acquire, which carries the data across the XCDs' L2
+// caches.
 #include "dump_dev.h"
 #include "fstage_dev.h"
 #include "xstage_dev.h"
@@ -99,8 +100,11 @@ __global__ __launch_bounds__(256, 2) void batch_kernel(const BJob *jobs, const u
                     }
                     __builtin_amdgcn_s_sleep(8);
                 }
-                // the producers' writes become visible to this workgroup
+                // the producers' writes become visible to this workgroup: the
+                // acquire invalidates this CU's and this XCD's caches, and the
+                // wait keeps every wave's loads after the barrier behind it
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                __builtin_amdgcn_s_waitcnt(0x0F70);
             }
             __syncthreads();
         }
@@ -156,12 +160,19 @@ __global__ __launch_bounds__(256, 2) void batch_kernel(const BJob *jobs, const u
                 break;
             }
         }
-        // publish this item's writes (every wave's, through the barrier and
-        // one agent-scope release), then count it
+        // Publish this item's writes, then count it.  Every wave first waits
+        // until its own stores have completed in its XCD's L2 (vmcnt(0); a
+        // workgroup-scope release does not wait for them), so that thread 0's
+        // agent-scope release after the barrier, which writes that L2 back,
+        // covers the writes of every wave and not only of wave 0.
+        __builtin_amdgcn_s_waitcnt(0x0F70);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __syncthreads();
         if (threadIdx.x == 0 && it.sig >= 0) {
+            // the agent-scope release writes the L2 back; the wait makes that
+            // write-back complete before the count can be seen
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __builtin_amdgcn_s_waitcnt(0x0F70);
             __hip_atomic_fetch_add(&ctr[it.sig], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }

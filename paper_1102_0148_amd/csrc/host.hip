@@ -121,6 +121,7 @@ struct corr_ctx {
     float *power = nullptr;
     int2 *regions = nullptr;
     unsigned long long *sat = nullptr;
+    unsigned *fticket = nullptr;  // F-stage tile-chunk counters
     // state
     int64_t accumulated = 0;
     int last_chunk = 0;
@@ -168,7 +169,7 @@ void free_ctx(corr_ctx *h) {
     if (h->graph) hipGraphDestroy(h->graph);
     if (h->cap_stream) hipStreamDestroy(h->cap_stream);
     void *bufs[] = {h->spec,   h->partial, h->acc,   h->stage,   h->tw,   h->scales, h->power,
-                    h->regions, h->sat,    h->bjobs, h->in_ptrs, h->items, h->bctr};
+                    h->regions, h->sat, h->fticket, h->bjobs, h->in_ptrs, h->items, h->bctr};
     for (void *p : bufs)
         if (p) hipFree(p);
     for (corr_ctx *j : h->jobs) free_ctx(j);
@@ -338,6 +339,7 @@ int process_one(corr_ctx *h, const uint8_t *in, hipStream_t st) {
         fa.scales = h->scales;
         fa.tw = h->tw;
         fa.sat = h->sat;
+        fa.ticket = h->fticket;
         fa.N = h->N;
         fa.a_pad = h->a_pad;
         fa.S = Sc;
@@ -457,6 +459,7 @@ corr_ctx *create_ctx(int N, int K, int S) {
     if ((e = hipMalloc(&h->stage, accb)) != hipSuccess) return bail(e, "hipMalloc(read stage)");
     if ((e = hipMalloc(&h->sat, sizeof(unsigned long long))) != hipSuccess) return bail(e, "hipMalloc(counter)");
     if ((e = hipMemset(h->sat, 0, sizeof(unsigned long long))) != hipSuccess) return bail(e, "hipMemset(counter)");
+    if ((e = hipMalloc(&h->fticket, kTicketBytes)) != hipSuccess) return bail(e, "hipMalloc(tile tickets)");
     return h;
 }
 
@@ -707,7 +710,9 @@ int batch_build(corr_ctx *b) {
         const int rb = h->nblk <= 3 ? h->nblk : (h->nblk % 2 == 0 ? 2 : 1);
         HIP_TRY(set_regions(h, rb), "regions");
         lds = std::max(lds, batch_lds_bytes(h->K, h->prec));
-        const int c0 = 2 + j * kBatchCounters;  // power, scales, F, X, dump
+        // this job's counters, indices into the counter array the kernel is
+        // given (after the ticket and the error flag): power, scales, F, X, dump
+        const int c0 = j * kBatchCounters;
         const int ga = h->tiles.f_group;
         const int ngroups = (h->N + ga - 1) / ga;
         const int ntq_used = round_up((h->S + h->TG - 1) / h->TG, 4);
@@ -790,7 +795,10 @@ int batch_build(corr_ctx *b) {
         if (j >= 2) items.insert(items.end(), dumps[j - 2].begin(), dumps[j - 2].end());
     }
     b->n_items = (int)items.size();
-    b->n_ctr = 2 + nj * kBatchCounters;
+    b->n_ctr = 2 + nj * kBatchCounters;  // ticket, error flag, then the job counters
+    for (const BItem &it : items)
+        if (it.wait >= nj * kBatchCounters || it.sig >= nj * kBatchCounters)
+            return fail(CORR_EHIP, "batch: work item counter index out of range");
     b->b_lds = lds;
     HIP_TRY(batch_prepare(lds), "hipFuncSetAttribute(batch)");
     const int maxb = batch_max_blocks(lds);

@@ -62,9 +62,20 @@ def test_batch_matches_oracle_and_single_job():
 
 def test_batch_graph_replays():
     """Replay the captured graph several times with eager work and
-    synchronisations between replays; every replay gives the same result."""
+    synchronisations between replays.  Every replay, the first included, is
+    checked: int8 jobs bit-exactly against the single-job path, float jobs
+    against the oracle, and every replay equals the first.  (The last job's
+    counters are the last of the counter array, and its dumps are the last
+    items; a wrong counter index there once showed only in the first run.)"""
     jobs = JOBS[:6]
     inputs = _inputs(jobs, seed0=200)
+    singles = {}
+    for j, (N, K, S, prec) in enumerate(jobs):
+        if prec == "int8":
+            c = corr.Correlator(N, K, S, precision=prec)
+            c.process(inputs[j])
+            singles[j] = c.read_cps_raw()
+            c.close()
     b = corr.Batch(jobs)
     first = None
     for rep in range(4):
@@ -74,11 +85,17 @@ def test_batch_graph_replays():
         scratch.mul_(2.0).sum().item()
         torch.cuda.synchronize()
         raws = [b.read_cps_raw(j) for j in range(len(jobs))]
+        print(f"\n[batch replay] {rep}", flush=True)
+        for j, (N, K, S, prec) in enumerate(jobs):
+            if prec == "int8":
+                np.testing.assert_array_equal(raws[j], singles[j], err_msg=f"replay {rep} job {j}")
+            elif rep == 0:
+                _check_job(raws[j], N, K, S, prec, inputs[j])
         if first is None:
             first = raws
         else:
             for j in range(len(jobs)):
-                np.testing.assert_array_equal(raws[j], first[j])
+                np.testing.assert_array_equal(raws[j], first[j], err_msg=f"replay {rep} job {j}")
 
 
 def test_batch_rejects_bad_input():
