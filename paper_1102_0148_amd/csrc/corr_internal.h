@@ -49,6 +49,7 @@ struct FArgs {
     const float *scales;      // int8: [N][M]
     const float2 *tw;         // W_M^j (j < M), W_2M^q (q < M/2), then M zero bytes
     unsigned long long *sat;  // int8 saturation counter
+    unsigned *ticket;         // records mode: 8 tile-chunk counters, zero at launch
     int N, a_pad, S;          // S = spectra in this chunk
     int ntq;                  // power mode: time tiles in the window
     int ngroups;              // antenna groups of GA covering [0, N)
@@ -56,10 +57,16 @@ struct FArgs {
     int tiles_per_wg;         // power mode: time tiles per workgroup
 };
 
+// Tile-chunk ticket counters of the records-mode F-stage: one per XCD, each on
+// its own 128-byte line.
+constexpr int kTicketStride = 32;
+constexpr size_t kTicketBytes = 8 * kTicketStride * sizeof(unsigned);
+
 // Launch the F-stage for complex length M = K (channels).  mode: 0 = spectra
 // records in precision `prec`, over as many persistent workgroups as stay
-// resident (`grid` ignored); 1 = power sums over the calibration window
-// (records not written), `grid` blocks.  Returns hipSuccess or the error.
+// resident (`grid` ignored; a.ticket zeroed first, on the same stream);
+// 1 = power sums over the calibration window (records not written), `grid`
+// blocks.  Returns hipSuccess or the error.
 hipError_t launch_fstage(int M, int prec, int ga, int power_mode, const FArgs &a, int grid,
                          hipStream_t st);
 int fstage_lds_bytes(int M, int prec, int ga);

@@ -13,13 +13,14 @@ __global__ __launch_bounds__(kThreads) void fstage_kernel(FArgs args) {
     if constexpr (!POWER) {
         // persistent workgroups; workgroup b runs on XCD b % 8 (round-robin
         // dispatch), and the tiles of XCD x are the range [x t8, (x+1) t8),
-        // dealt round-robin to its workgroups: tiles in flight on one XCD are
-        // neighbours (consecutive antenna groups of nearby time records) whose
-        // partial lines meet in one L2
-        const int nw8 = gridDim.x / 8;
+        // dealt in chunks by that XCD's ticket counter: tiles in flight on one
+        // XCD are neighbours (consecutive antenna groups of nearby time
+        // records) whose partial lines meet in one L2
+        __shared__ int s_tk[2];
         const int t8 = (args.ntiles + 7) / 8;
-        const int lo = (blockIdx.x % 8) * t8, hi = min(lo + t8, args.ntiles);
-        f_tiles<M, PREC, GA>(args, lo + blockIdx.x / 8, nw8, hi, zbuf, bbuf);
+        const int x = blockIdx.x % 8;
+        const int lo = x * t8, hi = min(lo + t8, args.ntiles);
+        f_tiles_dyn<M, PREC, GA>(args, lo, hi, args.ticket + kTicketStride * x, s_tk, zbuf, bbuf);
     } else {
         f_power_block<M>(args, blockIdx.x, zbuf, bbuf);
     }
@@ -42,6 +43,10 @@ hipError_t launch_one(const FArgs &a, int grid, hipStream_t st) {
             const int cap = per_cu * cus / 8 > 0 ? per_cu * cus / 8 : 1;
             const int need = (a.ntiles + 7) / 8;
             grid = 8 * (need < cap ? need : cap);
+        }
+        if (!POWER) {
+            const hipError_t z = launch_fill_zero(a.ticket, kTicketBytes, st);
+            if (z != hipSuccess) return z;
         }
         hipLaunchKernelGGL((fstage_kernel<M, PREC, GA, POWER>), dim3(grid), dim3(kThreads), 0, st, a);
         return hipGetLastError();

@@ -320,28 +320,89 @@ __device__ __forceinline__ void tile_ffts(const u32x4 (&raw)[ROUNDS], float2 *zb
     }
 }
 
+// Per-workgroup constants of a records tile loop: every pass twiddle of the
+// lane and W_2M^q of the thread's bin pairs (task t = bin pair q, antenna ga).
+template <int M, int PREC, int GA>
+struct TileConsts {
+    using Sh = FShape<M, PREC, GA, false>;
+    PassTw<M> ptw;
+    float2 bw[Sh::TPT];
+    __device__ __forceinline__ void load(const FArgs &args) {
+        const int tid = threadIdx.x;
+        ptw.load(tid % (M / 16), args.tw);
+#pragma unroll
+        for (int it = 0; it < Sh::TPT; ++it) {
+            const int t = tid + it * kThreads;
+            bw[it] = (Sh::NTASK % kThreads == 0 || t < Sh::NTASK) ? args.tw[M + t / GA] : make_float2(1.0f, 0.0f);
+        }
+    }
+};
+
+// int8 scales of the thread's bin pairs in antenna group g.  The loads are
+// unconditional, as in load_tile; antennas past N have zero spectra and take
+// antenna 0's scales.
+template <int M, int PREC, int GA>
+__device__ __forceinline__ void tile_scales(const FArgs &args, int g, float *slo, float *shi) {
+    using Sh = FShape<M, PREC, GA, false>;
+#pragma unroll
+    for (int it = 0; it < Sh::TPT; ++it) {
+        slo[it] = shi[it] = 1.0f;
+        if constexpr (PREC == kINT8) {
+            const int t = threadIdx.x + it * kThreads;
+            const bool ok = (Sh::NTASK % kThreads == 0 || t < Sh::NTASK) && g * GA + t % GA < args.N;
+            const int a = ok ? g * GA + t % GA : 0, q = ok ? t / GA : 0;
+            slo[it] = args.scales[(int64_t)a * M + q];
+            shi[it] = args.scales[(int64_t)a * M + (q == 0 ? M / 2 : M - q)];
+        }
+    }
+}
+
+// One tile (time record tq, antenna group g) of records from frames already
+// loaded: TS spectra of GA antennas transformed, turned into bins and written
+// as records.  The caller separates consecutive tiles with a barrier.
+template <int M, int PREC, int GA>
+__device__ __forceinline__ void tile_records(const FArgs &args, int tq, int g,
+                                             const u32x4 (&cur)[FShape<M, PREC, GA, false>::ROUNDS],
+                                             const TileConsts<M, PREC, GA> &k, const float *slo, const float *shi,
+                                             unsigned &nsat, float2 *zbuf, uint32_t *bbuf) {
+    using Sh = FShape<M, PREC, GA, false>;
+    constexpr int TS = Sh::TS, SLOT = Sh::SLOT, NTASK = Sh::NTASK, TPT = Sh::TPT;
+    const int tid = threadIdx.x;
+    tile_ffts<M, Sh::NF, Sh::ROUNDS>(cur, zbuf, bbuf, k.ptw);
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < TPT; ++it) {
+        const int t = tid + it * kThreads;
+        if (NTASK % kThreads != 0 && t >= NTASK) break;
+        const int ga = t % GA, q = t / GA;
+        const int a = g * GA + ga;
+        float lr[TS], li[TS], hr[TS], hi[TS];
+#pragma unroll
+        for (int ts = 0; ts < TS; ++ts) {
+            float2 xlo, xhi;
+            real_bins<M>(zbuf + (ts * GA + ga) * SLOT, q, k.bw[it], xlo, xhi);
+            lr[ts] = xlo.x; li[ts] = xlo.y; hr[ts] = xhi.x; hi[ts] = xhi.y;
+        }
+        const int clo = q, chi = q == 0 ? M / 2 : M - q;
+        const uint4 rlo = make_record<PREC, TS>(lr, li, slo[it], nsat);
+        const uint4 rhi = make_record<PREC, TS>(hr, hi, shi[it], nsat);
+        args.spec[rec_index(clo, tq, a, M, args.a_pad)] = rlo;
+        args.spec[rec_index(chi, tq, a, M, args.a_pad)] = rhi;
+    }
+}
+
 // Tiles t0, t0 + stride, ... below t1 of spectra records; tile = time record
-// tq * ngroups + antenna group g.  Each tile's TS spectra of GA antennas are
-// transformed, turned into bins and written as records.  The next tile's
-// frames are read while the current one is transformed, and the twiddles are
-// loaded once, so neither latency sits between a tile's stages.
+// tq * ngroups + antenna group g.  The next tile's frames are read while the
+// current one is transformed, and the twiddles are loaded once, so neither
+// latency sits between a tile's stages.
 template <int M, int PREC, int GA>
 __device__ __forceinline__ void f_tiles(const FArgs &args, int t0, int stride, int t1, float2 *zbuf,
                                         uint32_t *bbuf) {
     using Sh = FShape<M, PREC, GA, false>;
-    constexpr int TS = Sh::TS, SLOT = Sh::SLOT, NF = Sh::NF, ROUNDS = Sh::ROUNDS;
-    constexpr int NTASK = Sh::NTASK, TPT = Sh::TPT;
+    constexpr int TS = Sh::TS, NF = Sh::NF, ROUNDS = Sh::ROUNDS, TPT = Sh::TPT;
     if (t0 >= t1) return;
-    const int tid = threadIdx.x;
-    PassTw<M> ptw;
-    ptw.load(tid % (M / 16), args.tw);
-    // W_2M^q of this thread's bin pairs (task t = bin pair q, antenna ga)
-    float2 bw[TPT];
-#pragma unroll
-    for (int it = 0; it < TPT; ++it) {
-        const int t = tid + it * kThreads;
-        bw[it] = (NTASK % kThreads == 0 || t < NTASK) ? args.tw[M + t / GA] : make_float2(1.0f, 0.0f);
-    }
+    TileConsts<M, PREC, GA> k;
+    k.load(args);
     u32x4 raw[ROUNDS];
     load_tile<M, GA, TS, NF, ROUNDS>(args, t0 / args.ngroups, t0 % args.ngroups, raw);
     // Wait for the first frames here, before the loop: otherwise the wait at
@@ -353,47 +414,78 @@ __device__ __forceinline__ void f_tiles(const FArgs &args, int t0, int stride, i
     for (int tile = t0; tile < t1; tile += stride) {
         const int tq = tile / args.ngroups, g = tile % args.ngroups;
         float slo[TPT], shi[TPT];
-#pragma unroll
-        for (int it = 0; it < TPT; ++it) {
-            slo[it] = shi[it] = 1.0f;
-            if constexpr (PREC == kINT8) {
-                // unconditional loads, as in load_tile; antennas past N have
-                // zero spectra and take antenna 0's scales
-                const int t = tid + it * kThreads;
-                const bool ok = (NTASK % kThreads == 0 || t < NTASK) && g * GA + t % GA < args.N;
-                const int a = ok ? g * GA + t % GA : 0, q = ok ? t / GA : 0;
-                slo[it] = args.scales[(int64_t)a * M + q];
-                shi[it] = args.scales[(int64_t)a * M + (q == 0 ? M / 2 : M - q)];
-            }
-        }
+        tile_scales<M, PREC, GA>(args, g, slo, shi);
         u32x4 cur[ROUNDS];
 #pragma unroll
         for (int r = 0; r < ROUNDS; ++r) cur[r] = raw[r];
         // the last tile re-reads its own frames rather than branch around the load
         const int nxt = tile + stride < t1 ? tile + stride : tile;
         load_tile<M, GA, TS, NF, ROUNDS>(args, nxt / args.ngroups, nxt % args.ngroups, raw);
-        tile_ffts<M, NF, ROUNDS>(cur, zbuf, bbuf, ptw);
-        __syncthreads();
-#pragma unroll
-        for (int it = 0; it < TPT; ++it) {
-            const int t = tid + it * kThreads;
-            if (NTASK % kThreads != 0 && t >= NTASK) break;
-            const int ga = t % GA, q = t / GA;
-            const int a = g * GA + ga;
-            float lr[TS], li[TS], hr[TS], hi[TS];
-#pragma unroll
-            for (int ts = 0; ts < TS; ++ts) {
-                float2 xlo, xhi;
-                real_bins<M>(zbuf + (ts * GA + ga) * SLOT, q, bw[it], xlo, xhi);
-                lr[ts] = xlo.x; li[ts] = xlo.y; hr[ts] = xhi.x; hi[ts] = xhi.y;
-            }
-            const int clo = q, chi = q == 0 ? M / 2 : M - q;
-            const uint4 rlo = make_record<PREC, TS>(lr, li, slo[it], nsat);
-            const uint4 rhi = make_record<PREC, TS>(hr, hi, shi[it], nsat);
-            args.spec[rec_index(clo, tq, a, M, args.a_pad)] = rlo;
-            args.spec[rec_index(chi, tq, a, M, args.a_pad)] = rhi;
-        }
+        tile_records<M, PREC, GA>(args, tq, g, cur, k, slo, shi, nsat, zbuf, bbuf);
         __syncthreads();  // zbuf and bbuf are rewritten by the next tile
+    }
+    if constexpr (PREC == kINT8) {
+        if (nsat) atomicAdd(args.sat, (unsigned long long)nsat);
+    }
+}
+
+// Tiles [lo, hi) of spectra records dealt out in chunks of kFChunk consecutive
+// tiles by the ticket counter *ctr (zero at launch): a workgroup that runs
+// faster than its neighbours on the CU takes more chunks, so all finish
+// together.  Thread 0 takes the ticket of the chunk after next when a chunk
+// starts and publishes it in s_tk before the barrier that ends the chunk's
+// first tile; it is read once the chunk's last tile is done, so the atomic's
+// latency hides behind a tile.
+constexpr int kFChunk = 4;
+template <int M, int PREC, int GA>
+__device__ __forceinline__ void f_tiles_dyn(const FArgs &args, int lo, int hi, unsigned *ctr, int *s_tk,
+                                            float2 *zbuf, uint32_t *bbuf) {
+    using Sh = FShape<M, PREC, GA, false>;
+    constexpr int TS = Sh::TS, NF = Sh::NF, ROUNDS = Sh::ROUNDS, TPT = Sh::TPT;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        s_tk[0] = (int)atomicAdd(ctr, 1u);
+        s_tk[1] = (int)atomicAdd(ctr, 1u);
+    }
+    __syncthreads();
+    int tile = lo + s_tk[0] * kFChunk;   // current tile
+    int nchunk = lo + s_tk[1] * kFChunk;  // first tile of the next chunk
+    __syncthreads();                      // s_tk[0] is rewritten below
+    if (tile >= hi) return;
+    int cend = min(tile + kFChunk, hi);
+    TileConsts<M, PREC, GA> k;
+    k.load(args);
+    u32x4 raw[ROUNDS];
+    load_tile<M, GA, TS, NF, ROUNDS>(args, tile / args.ngroups, tile % args.ngroups, raw);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // as in f_tiles
+    unsigned nsat = 0, tk = 0;
+    bool first = true;
+    for (;;) {
+        // an increment (not an add) so the compiler's wave-level atomic
+        // rewriting, which reads the result back at once, leaves it alone
+        if (first && tid == 0) tk = atomicInc(ctr, 0xffffffffu);
+        const int tq = tile / args.ngroups, g = tile % args.ngroups;
+        float slo[TPT], shi[TPT];
+        tile_scales<M, PREC, GA>(args, g, slo, shi);
+        u32x4 cur[ROUNDS];
+#pragma unroll
+        for (int r = 0; r < ROUNDS; ++r) cur[r] = raw[r];
+        const bool more = tile + 1 < cend;
+        const int nxt = more ? tile + 1 : (nchunk < hi ? nchunk : tile);
+        load_tile<M, GA, TS, NF, ROUNDS>(args, nxt / args.ngroups, nxt % args.ngroups, raw);
+        tile_records<M, PREC, GA>(args, tq, g, cur, k, slo, shi, nsat, zbuf, bbuf);
+        if (first && tid == 0) s_tk[0] = (int)tk;
+        __syncthreads();  // zbuf and bbuf are rewritten by the next tile; s_tk published
+        if (more) {
+            ++tile;
+            first = false;
+        } else {
+            if (nchunk >= hi) break;
+            tile = nchunk;
+            cend = min(tile + kFChunk, hi);
+            nchunk = lo + s_tk[0] * kFChunk;
+            first = true;
+        }
     }
     if constexpr (PREC == kINT8) {
         if (nsat) atomicAdd(args.sat, (unsigned long long)nsat);
