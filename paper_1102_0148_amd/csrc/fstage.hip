@@ -13,8 +13,8 @@ __global__ __launch_bounds__(kThreads) void fstage_kernel(FArgs args) {
     if constexpr (!POWER) {
         // persistent workgroups; workgroup b runs on XCD b % 8 (round-robin
         // dispatch), and the tiles of XCD x are the range [x t8, (x+1) t8),
-        // dealt in chunks by that XCD's ticket counter: tiles in flight on one
-        // XCD are neighbours (consecutive antenna groups of nearby time
+        // dealt one by one by that XCD's ticket counter: tiles in flight on
+        // one XCD are neighbours (consecutive antenna groups of nearby time
         // records) whose partial lines meet in one L2
         __shared__ int s_tk[2];
         const int t8 = (args.ntiles + 7) / 8;

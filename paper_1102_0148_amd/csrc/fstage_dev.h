@@ -429,14 +429,13 @@ __device__ __forceinline__ void f_tiles(const FArgs &args, int t0, int stride, i
     }
 }
 
-// Tiles [lo, hi) of spectra records dealt out in chunks of kFChunk consecutive
-// tiles by the ticket counter *ctr (zero at launch): a workgroup that runs
-// faster than its neighbours on the CU takes more chunks, so all finish
-// together.  Thread 0 takes the ticket of the chunk after next when a chunk
-// starts and publishes it in s_tk before the barrier that ends the chunk's
-// first tile; it is read once the chunk's last tile is done, so the atomic's
-// latency hides behind a tile.
-constexpr int kFChunk = 4;
+// Tiles [lo, hi) of spectra records dealt out one per ticket by the counter
+// *ctr (zero at launch).  Tickets are taken in order, so the tiles in flight
+// on an XCD stay neighbours whose partial record lines meet in its L2, and a
+// workgroup that runs faster than its neighbours on the CU takes more tiles,
+// so all finish together.  Thread 0 takes the ticket of the tile after next
+// when a tile starts and publishes it in s_tk before the barrier that ends the
+// tile, so the atomic's latency hides behind a tile.
 template <int M, int PREC, int GA>
 __device__ __forceinline__ void f_tiles_dyn(const FArgs &args, int lo, int hi, unsigned *ctr, int *s_tk,
                                             float2 *zbuf, uint32_t *bbuf) {
@@ -448,44 +447,34 @@ __device__ __forceinline__ void f_tiles_dyn(const FArgs &args, int lo, int hi, u
         s_tk[1] = (int)atomicAdd(ctr, 1u);
     }
     __syncthreads();
-    int tile = lo + s_tk[0] * kFChunk;   // current tile
-    int nchunk = lo + s_tk[1] * kFChunk;  // first tile of the next chunk
-    __syncthreads();                      // s_tk[0] is rewritten below
+    int tile = lo + s_tk[0], next = lo + s_tk[1];
+    __syncthreads();  // s_tk[0] is rewritten below
     if (tile >= hi) return;
-    int cend = min(tile + kFChunk, hi);
     TileConsts<M, PREC, GA> k;
     k.load(args);
     u32x4 raw[ROUNDS];
     load_tile<M, GA, TS, NF, ROUNDS>(args, tile / args.ngroups, tile % args.ngroups, raw);
     __builtin_amdgcn_s_waitcnt(0x0F70);  // as in f_tiles
     unsigned nsat = 0, tk = 0;
-    bool first = true;
     for (;;) {
         // an increment (not an add) so the compiler's wave-level atomic
         // rewriting, which reads the result back at once, leaves it alone
-        if (first && tid == 0) tk = atomicInc(ctr, 0xffffffffu);
+        if (tid == 0) tk = atomicInc(ctr, 0xffffffffu);
         const int tq = tile / args.ngroups, g = tile % args.ngroups;
         float slo[TPT], shi[TPT];
         tile_scales<M, PREC, GA>(args, g, slo, shi);
         u32x4 cur[ROUNDS];
 #pragma unroll
         for (int r = 0; r < ROUNDS; ++r) cur[r] = raw[r];
-        const bool more = tile + 1 < cend;
-        const int nxt = more ? tile + 1 : (nchunk < hi ? nchunk : tile);
-        load_tile<M, GA, TS, NF, ROUNDS>(args, nxt / args.ngroups, nxt % args.ngroups, raw);
+        // the last tile re-reads its own frames rather than branch around the load
+        const int pf = next < hi ? next : tile;
+        load_tile<M, GA, TS, NF, ROUNDS>(args, pf / args.ngroups, pf % args.ngroups, raw);
         tile_records<M, PREC, GA>(args, tq, g, cur, k, slo, shi, nsat, zbuf, bbuf);
-        if (first && tid == 0) s_tk[0] = (int)tk;
+        if (tid == 0) s_tk[0] = (int)tk;
         __syncthreads();  // zbuf and bbuf are rewritten by the next tile; s_tk published
-        if (more) {
-            ++tile;
-            first = false;
-        } else {
-            if (nchunk >= hi) break;
-            tile = nchunk;
-            cend = min(tile + kFChunk, hi);
-            nchunk = lo + s_tk[0] * kFChunk;
-            first = true;
-        }
+        if (next >= hi) break;
+        tile = next;
+        next = lo + s_tk[0];
     }
     if constexpr (PREC == kINT8) {
         if (nsat) atomicAdd(args.sat, (unsigned long long)nsat);
