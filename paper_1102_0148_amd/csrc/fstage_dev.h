@@ -183,9 +183,13 @@ __device__ __forceinline__ float nib(uint32_t w, int off) {
 }
 
 // Pack TS spectra of one (channel, antenna) into a 16-byte record
-// [re x TS][im x TS] of the precision's type.  int8: q = clamp(rint(x sc)).
+// [re x TS][im x TS] of the precision's type.  int8: the record holds
+// q = clamp(rint(x sc), -127, 127), rounding to nearest even, with re[] and
+// im[] here already multiplied by two and sc halved (both exact, so x sc is
+// the same float); wsat (wave-uniform) counts the values with |x sc| >= 127.5,
+// those whose rounded magnitude exceeds 127.
 template <int PREC, int TS>
-__device__ __forceinline__ uint4 make_record(const float *re, const float *im, float sc, unsigned &nsat) {
+__device__ __forceinline__ uint4 make_record(const float *re, const float *im, float sc, unsigned &wsat) {
     uint4 out;
     if constexpr (PREC == kFP32) {
         static_assert(TS == 2, "fp32 record");
@@ -202,34 +206,53 @@ __device__ __forceinline__ uint4 make_record(const float *re, const float *im, f
         __builtin_memcpy(&out, h, 16);
     } else {
         static_assert(TS == 8, "int8 record");
-        int8_t b[16];
+        // rint and the clamp to +-127 commute, so clamp first; adding 1.5 * 2^23
+        // then rounds to the nearest integer (ties to even) and leaves it, as
+        // two's complement, in the low byte of the sum
+        uint32_t w[4];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            float vr = rintf(re[t] * sc), vi = rintf(im[t] * sc);
-            nsat += (fabsf(vr) > 127.0f) + (fabsf(vi) > 127.0f);
-            b[t] = (int8_t)(int)fminf(fmaxf(vr, -127.0f), 127.0f);
-            b[8 + t] = (int8_t)(int)fminf(fmaxf(vi, -127.0f), 127.0f);
+        for (int k = 0; k < 4; ++k) {
+            const float *x = k < 2 ? re + 4 * k : im + 4 * (k - 2);
+            uint32_t b[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const float v = x[t] * sc;
+                wsat += (unsigned)__popcll(__ballot(fabsf(v) >= 127.5f));
+                b[t] = __float_as_uint(__builtin_amdgcn_fmed3f(v, -127.0f, 127.0f) + 12582912.0f);
+            }
+            // low bytes of b[0..3] -> bytes 0..3 of the word
+            w[k] = __builtin_amdgcn_perm(b[1], b[0], 0x0c0c0400u) | __builtin_amdgcn_perm(b[3], b[2], 0x04000c0cu);
         }
-        __builtin_memcpy(&out, b, 16);
+        out = make_uint4(w[0], w[1], w[2], w[3]);
     }
     return out;
 }
 
 // Real-input bins q and K-q (q = 0: bins 0 and K/2) from a transform slot;
-// w = W_2K^q.
-template <int M>
+// w = W_2K^q.  TWICE returns both bins multiplied by two (exact), which
+// saves the halving where a scale follows.
+template <int M, bool TWICE = false>
 __device__ __forceinline__ void real_bins(const float2 *zs, int q, float2 w, float2 &xlo, float2 &xhi) {
     if (q == 0) {
         const float2 z0 = zs[0], zh = zs[pad(M / 2)];
         xlo = make_float2(z0.x + z0.y, 0.0f);
         xhi = make_float2(zh.x, -zh.y);
+        if constexpr (TWICE) {
+            xlo.x *= 2.0f;
+            xhi = make_float2(2.0f * xhi.x, 2.0f * xhi.y);
+        }
     } else {
         const float2 z0 = zs[pad(q)], z1 = zs[pad(M - q)];
         const float2 A = make_float2(z0.x + z1.x, z0.y - z1.y);
         const float2 B = make_float2(z0.x - z1.x, z0.y + z1.y);
         const float2 C = cmul(B, w);
-        xlo = make_float2(0.5f * (A.x + C.y), 0.5f * (A.y - C.x));
-        xhi = make_float2(0.5f * (A.x - C.y), 0.5f * (-A.y - C.x));
+        if constexpr (TWICE) {
+            xlo = make_float2(A.x + C.y, A.y - C.x);
+            xhi = make_float2(A.x - C.y, -A.y - C.x);
+        } else {
+            xlo = make_float2(0.5f * (A.x + C.y), 0.5f * (A.y - C.x));
+            xhi = make_float2(0.5f * (A.x - C.y), 0.5f * (-A.y - C.x));
+        }
     }
 }
 
@@ -338,7 +361,7 @@ struct TileConsts {
     }
 };
 
-// int8 scales of the thread's bin pairs in antenna group g.  The loads are
+// int8 scales of the thread's bin pairs in antenna group g, halved.  The loads are
 // unconditional, as in load_tile; antennas past N have zero spectra and take
 // antenna 0's scales.
 template <int M, int PREC, int GA>
@@ -351,8 +374,9 @@ __device__ __forceinline__ void tile_scales(const FArgs &args, int g, float *slo
             const int t = threadIdx.x + it * kThreads;
             const bool ok = (Sh::NTASK % kThreads == 0 || t < Sh::NTASK) && g * GA + t % GA < args.N;
             const int a = ok ? g * GA + t % GA : 0, q = ok ? t / GA : 0;
-            slo[it] = args.scales[(int64_t)a * M + q];
-            shi[it] = args.scales[(int64_t)a * M + (q == 0 ? M / 2 : M - q)];
+            // halved: the bins come doubled (real_bins<M, true>)
+            slo[it] = 0.5f * args.scales[(int64_t)a * M + q];
+            shi[it] = 0.5f * args.scales[(int64_t)a * M + (q == 0 ? M / 2 : M - q)];
         }
     }
 }
@@ -364,7 +388,7 @@ template <int M, int PREC, int GA>
 __device__ __forceinline__ void tile_records(const FArgs &args, int tq, int g,
                                              const u32x4 (&cur)[FShape<M, PREC, GA, false>::ROUNDS],
                                              const TileConsts<M, PREC, GA> &k, const float *slo, const float *shi,
-                                             unsigned &nsat, float2 *zbuf, uint32_t *bbuf) {
+                                             unsigned &wsat, float2 *zbuf, uint32_t *bbuf) {
     using Sh = FShape<M, PREC, GA, false>;
     constexpr int TS = Sh::TS, SLOT = Sh::SLOT, NTASK = Sh::NTASK, TPT = Sh::TPT;
     const int tid = threadIdx.x;
@@ -380,12 +404,12 @@ __device__ __forceinline__ void tile_records(const FArgs &args, int tq, int g,
 #pragma unroll
         for (int ts = 0; ts < TS; ++ts) {
             float2 xlo, xhi;
-            real_bins<M>(zbuf + (ts * GA + ga) * SLOT, q, k.bw[it], xlo, xhi);
+            real_bins<M, PREC == kINT8>(zbuf + (ts * GA + ga) * SLOT, q, k.bw[it], xlo, xhi);
             lr[ts] = xlo.x; li[ts] = xlo.y; hr[ts] = xhi.x; hi[ts] = xhi.y;
         }
         const int clo = q, chi = q == 0 ? M / 2 : M - q;
-        const uint4 rlo = make_record<PREC, TS>(lr, li, slo[it], nsat);
-        const uint4 rhi = make_record<PREC, TS>(hr, hi, shi[it], nsat);
+        const uint4 rlo = make_record<PREC, TS>(lr, li, slo[it], wsat);
+        const uint4 rhi = make_record<PREC, TS>(hr, hi, shi[it], wsat);
         args.spec[rec_index(clo, tq, a, M, args.a_pad)] = rlo;
         args.spec[rec_index(chi, tq, a, M, args.a_pad)] = rhi;
     }
@@ -410,7 +434,7 @@ __device__ __forceinline__ void f_tiles(const FArgs &args, int t0, int stride, i
     // memory operation, and each tile would wait for the previous tile's
     // record stores to land.  (vmcnt(0), expcnt and lgkmcnt left alone.)
     __builtin_amdgcn_s_waitcnt(0x0F70);
-    unsigned nsat = 0;
+    unsigned wsat = 0;  // saturated int8 values of this wave
     for (int tile = t0; tile < t1; tile += stride) {
         const int tq = tile / args.ngroups, g = tile % args.ngroups;
         float slo[TPT], shi[TPT];
@@ -421,11 +445,11 @@ __device__ __forceinline__ void f_tiles(const FArgs &args, int t0, int stride, i
         // the last tile re-reads its own frames rather than branch around the load
         const int nxt = tile + stride < t1 ? tile + stride : tile;
         load_tile<M, GA, TS, NF, ROUNDS>(args, nxt / args.ngroups, nxt % args.ngroups, raw);
-        tile_records<M, PREC, GA>(args, tq, g, cur, k, slo, shi, nsat, zbuf, bbuf);
+        tile_records<M, PREC, GA>(args, tq, g, cur, k, slo, shi, wsat, zbuf, bbuf);
         __syncthreads();  // zbuf and bbuf are rewritten by the next tile
     }
     if constexpr (PREC == kINT8) {
-        if (nsat) atomicAdd(args.sat, (unsigned long long)nsat);
+        if ((threadIdx.x & 63) == 0 && wsat) atomicAdd(args.sat, (unsigned long long)wsat);
     }
 }
 
@@ -455,7 +479,7 @@ __device__ __forceinline__ void f_tiles_dyn(const FArgs &args, int lo, int hi, u
     u32x4 raw[ROUNDS];
     load_tile<M, GA, TS, NF, ROUNDS>(args, tile / args.ngroups, tile % args.ngroups, raw);
     __builtin_amdgcn_s_waitcnt(0x0F70);  // as in f_tiles
-    unsigned nsat = 0, tk = 0;
+    unsigned wsat = 0, tk = 0;  // saturated int8 values of this wave; thread 0's ticket
     for (;;) {
         // an increment (not an add) so the compiler's wave-level atomic
         // rewriting, which reads the result back at once, leaves it alone
@@ -469,7 +493,7 @@ __device__ __forceinline__ void f_tiles_dyn(const FArgs &args, int lo, int hi, u
         // the last tile re-reads its own frames rather than branch around the load
         const int pf = next < hi ? next : tile;
         load_tile<M, GA, TS, NF, ROUNDS>(args, pf / args.ngroups, pf % args.ngroups, raw);
-        tile_records<M, PREC, GA>(args, tq, g, cur, k, slo, shi, nsat, zbuf, bbuf);
+        tile_records<M, PREC, GA>(args, tq, g, cur, k, slo, shi, wsat, zbuf, bbuf);
         if (tid == 0) s_tk[0] = (int)tk;
         __syncthreads();  // zbuf and bbuf are rewritten by the next tile; s_tk published
         if (next >= hi) break;
@@ -477,7 +501,7 @@ __device__ __forceinline__ void f_tiles_dyn(const FArgs &args, int lo, int hi, u
         next = lo + s_tk[0];
     }
     if constexpr (PREC == kINT8) {
-        if (nsat) atomicAdd(args.sat, (unsigned long long)nsat);
+        if ((threadIdx.x & 63) == 0 && wsat) atomicAdd(args.sat, (unsigned long long)wsat);
     }
 }
 
