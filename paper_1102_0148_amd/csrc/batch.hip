@@ -6,8 +6,7 @@
 // of every job.  Each workgroup repeatedly takes the next ticket; an item
 // whose inputs come from earlier items waits on a per-job counter, and a
 // finished item increments its counter.  An item only ever waits for items
-// with smaller tickets, which running workgroups already hold, so the queue
-// always drains.  Counters are bumped with an agent-scope release and read
+// with smaller tickets, so the queue always drains (see the kernel).  Counters are bumped with an agent-scope release and read
 // with an agent-scope acquire, which carries the data across the XCDs' L2
 // caches.
 #include "dump_dev.h"
@@ -83,19 +82,37 @@ __global__ __launch_bounds__(256, 2) void batch_kernel(const BJob *jobs, const u
     extern __shared__ __attribute__((aligned(16))) char lds[];
     __shared__ int s_item;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // Thread 0 only: the ticket of the next item, taken while the current one
+    // runs so the atomic's latency hides behind an item (an increment, which
+    // the compiler's wave-level atomic rewriting leaves asynchronous), and the
+    // last counter wait it satisfied.  Holding one ticket ahead keeps the
+    // queue deadlock-free: the smallest unfinished ticket is always some
+    // workgroup's current item, and everything it waits for has a smaller
+    // ticket, so it is finished.
+    unsigned next = 0, seen_val = 0;
+    int seen_ctr = -1;
+    if (threadIdx.x == 0) next = atomicInc(ticket, 0xffffffffu);
     for (;;) {
-        if (threadIdx.x == 0) s_item = (int)atomicAdd(ticket, 1u);
+        if (threadIdx.x == 0) {
+            s_item = (int)next;
+            next = atomicInc(ticket, 0xffffffffu);
+        }
         __syncthreads();
         const int t = s_item;
         __syncthreads();  // every thread has read s_item before it is reused
         if (t >= n_items) break;
         const BItem it = items[t];
         if (it.wait >= 0) {
-            if (threadIdx.x == 0) {
+            // counters only grow, so a wait this workgroup has already seen
+            // satisfied (and acquired) needs neither the spin nor another
+            // cache invalidate
+            if (threadIdx.x == 0 && !(it.wait == seen_ctr && (unsigned)it.wait_val <= seen_val)) {
                 unsigned spins = 0;
+                bool ok = true;
                 while (load_relaxed(&ctr[it.wait]) < (unsigned)it.wait_val) {
                     if (++spins > kBatchSpinLimit) {
                         atomicOr(err, 1u);
+                        ok = false;
                         break;
                     }
                     __builtin_amdgcn_s_sleep(8);
@@ -105,6 +122,10 @@ __global__ __launch_bounds__(256, 2) void batch_kernel(const BJob *jobs, const u
                 // wait keeps every wave's loads after the barrier behind it
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 __builtin_amdgcn_s_waitcnt(0x0F70);
+                if (ok) {
+                    seen_ctr = it.wait;
+                    seen_val = (unsigned)it.wait_val;
+                }
             }
             __syncthreads();
         }

@@ -124,8 +124,11 @@ struct BItem {
 };
 constexpr int kBatchCounters = 5;  // per job: power, scales, F, X, dump
 
-// Items per tile range, elements per scale / dump item.
+// Tiles per F item (at least 16, and at most 64 once a job has enough tiles
+// to keep every workgroup busy), elements per scale and per dump item.
 constexpr int kBatchTilesPerItem = 16;
+constexpr int kBatchMaxTilesPerItem = 64;
+constexpr int kBatchScaleElemsPerItem = 256;
 constexpr int kBatchElemsPerItem = 2048;
 // spin limit of a dependency wait (about a second); past it the kernel
 // records an error and goes on, so every wave always exits

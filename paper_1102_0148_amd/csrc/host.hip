@@ -768,14 +768,17 @@ int batch_build(corr_ctx *b) {
             d.nparts = (d.p.ntq + kCalibTilesPerWG - 1) / kCalibTilesPerWG;
             const int n_power = d.p.ngroups * d.nparts;
             for (int i = 0; i < n_power; ++i) power.push_back(BItem{BI_POWER, j, i, 0, -1, 0, c0 + 0, 0});
-            for (int e = 0; e < d.sc_n; e += kBatchElemsPerItem, ++n_scales)
-                scales.push_back(BItem{BI_SCALES, j, e, std::min(e + kBatchElemsPerItem, d.sc_n), c0 + 0, n_power,
-                                       c0 + 1, 0});
+            for (int e = 0; e < d.sc_n; e += kBatchScaleElemsPerItem, ++n_scales)
+                scales.push_back(BItem{BI_SCALES, j, e, std::min(e + kBatchScaleElemsPerItem, d.sc_n), c0 + 0,
+                                       n_power, c0 + 1, 0});
         }
+        // longer F items amortise each item's fixed costs (twiddles, the first
+        // frames' latency, the publish) once a job has tiles to spare
+        const int tpi = std::max(kBatchTilesPerItem, std::min(kBatchMaxTilesPerItem, d.f.ntiles / 1024));
         int n_f = 0;
-        for (int t = 0; t < d.f.ntiles; t += kBatchTilesPerItem, ++n_f)
-            fitems[j].push_back(BItem{BI_F, j, t, std::min(t + kBatchTilesPerItem, d.f.ntiles),
-                                   h->prec == kINT8 ? c0 + 1 : -1, n_scales, c0 + 2, 0});
+        for (int t = 0; t < d.f.ntiles; t += tpi, ++n_f)
+            fitems[j].push_back(BItem{BI_F, j, t, std::min(t + tpi, d.f.ntiles), h->prec == kINT8 ? c0 + 1 : -1,
+                                   n_scales, c0 + 2, 0});
         const int wd = (h->n_diag * h->K * xa.nsplit + 3) / 4, wo = (h->n_off * h->K * xa.nsplit + 3) / 4;
         for (int x = 0; x < wd; ++x) xitems[j].push_back(BItem{BI_XD, j, x, 0, c0 + 2, n_f, c0 + 3, 0});
         for (int x = 0; x < wo; ++x) xitems[j].push_back(BItem{BI_XO, j, x, 0, c0 + 2, n_f, c0 + 3, 0});
