@@ -4,8 +4,18 @@
 namespace corr {
 namespace {
 
+// Two workgroups per CU (two waves per SIMD) keep the accumulators in
+// ordinary VGPRs (without the bound the compiler splits them across VGPRs and
+// AGPRs, and the larger regions fall to one wave per SIMD); the fp32
+// off-diagonal 4 x 4-block region and the fp32 6-block diagonal region need
+// more than 256 registers and keep the default.
 template <int PREC, int RB, bool DIAG>
-__global__ __launch_bounds__(256) void xstage_kernel(XArgs a) {
+constexpr int x_min_blocks() {
+    return (PREC == kFP32 && ((RB >= 4 && !DIAG) || RB >= 6)) ? 1 : 2;
+}
+
+template <int PREC, int RB, bool DIAG>
+__global__ __launch_bounds__(256, (x_min_blocks<PREC, RB, DIAG>())) void xstage_kernel(XArgs a) {
     __shared__ float tbuf[4][16 * 17];
     // wave-uniform values live in scalar registers, so the loops have scalar
     // control flow
