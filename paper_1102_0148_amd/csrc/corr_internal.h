@@ -79,13 +79,15 @@ struct XArgs {
     void *partial;       // [nsplit][K][nb] float2 (fp32/fp16) or int2 (int8)
     const int2 *regions; // (I0, J0) block coordinates of each region
     int nregions;
+    int n_diag;          // launches of both kinds: regions [0, n_diag) are diagonal
     int N, a_pad, K, ntq, nb;
     int nsplit;
     int nkb;             // k-blocks in the chunk = ntq / 4
 };
-// rb: region side in 16-antenna blocks; diag: regions on the diagonal
-// (upper-triangle pairs only) or off the diagonal (full rb x rb).
-hipError_t launch_xstage(int prec, int rb, int diag, const XArgs &a, hipStream_t st);
+// rb: region side in 16-antenna blocks; kind 1: regions on the diagonal
+// (upper-triangle pairs only), 0: off the diagonal (full rb x rb), 2: both,
+// the first a.n_diag regions diagonal (rb 2..4).
+hipError_t launch_xstage(int prec, int rb, int kind, const XArgs &a, hipStream_t st);
 
 // ---------------------------------------------------------------- dump etc.
 // acc[f][bl] (double2) += sum over splits of partial[sp][f][bl], in split order.

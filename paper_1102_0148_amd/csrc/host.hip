@@ -282,12 +282,23 @@ int launch_x_and_dump(corr_ctx *h, const uint4 *spec, int ntq, int nkb, hipStrea
     xa.nkb = nkb;
     timer_begin(h, 2, st);
     xa.regions = h->regions;
-    xa.nregions = h->n_diag;
-    HIP_TRY(launch_xstage(h->prec, h->rb, 1, xa, st), "X-stage launch");
-    if (h->n_off) {
-        xa.regions = h->regions + h->n_diag;
-        xa.nregions = h->n_off;
-        HIP_TRY(launch_xstage(h->prec, h->rb, 0, xa, st), "X-stage launch");
+    xa.n_diag = h->n_diag;
+    if (h->n_off && h->prec != kFP32) {
+        // one launch over every region of a channel (diagonal ones first), so
+        // the regions that share records read them from HBM once, through one
+        // L2: the int8 and fp16 forms are bound by that traffic
+        xa.nregions = h->n_diag + h->n_off;
+        HIP_TRY(launch_xstage(h->prec, h->rb, 2, xa, st), "X-stage launch");
+    } else {
+        // fp32 is bound by MFMA rate, and its diagonal regions keep more waves
+        // per SIMD in a launch of their own
+        xa.nregions = h->n_diag;
+        HIP_TRY(launch_xstage(h->prec, h->rb, 1, xa, st), "X-stage launch");
+        if (h->n_off) {
+            xa.regions = h->regions + h->n_diag;
+            xa.nregions = h->n_off;
+            HIP_TRY(launch_xstage(h->prec, h->rb, 0, xa, st), "X-stage launch");
+        }
     }
     timer_end(h, st);
     h->launches_x++;

@@ -4,49 +4,73 @@
 namespace corr {
 namespace {
 
+// Region kinds of a launch: off-diagonal, diagonal, or both (regions
+// [0, n_diag) diagonal, the rest off-diagonal), which lets every region of a
+// channel read its records through one L2 in one launch.
+constexpr int kOffDiag = 0, kDiag = 1, kBoth = 2;
+
 // Two workgroups per CU (two waves per SIMD) keep the accumulators in
 // ordinary VGPRs (without the bound the compiler splits them across VGPRs and
 // AGPRs, and the larger regions fall to one wave per SIMD); the fp32
 // off-diagonal 4 x 4-block region and the fp32 6-block diagonal region need
 // more than 256 registers and keep the default.
-template <int PREC, int RB, bool DIAG>
+template <int PREC, int RB, int KIND>
 constexpr int x_min_blocks() {
-    return (PREC == kFP32 && ((RB >= 4 && !DIAG) || RB >= 6)) ? 1 : 2;
+    return (PREC == kFP32 && ((RB >= 4 && KIND != kDiag) || RB >= 6)) ? 1 : 2;
 }
 
-template <int PREC, int RB, bool DIAG>
-__global__ __launch_bounds__(256, (x_min_blocks<PREC, RB, DIAG>())) void xstage_kernel(XArgs a) {
+template <int PREC, int RB, int KIND>
+__global__ __launch_bounds__(256, (x_min_blocks<PREC, RB, KIND>())) void xstage_kernel(XArgs a) {
     __shared__ float tbuf[4][16 * 17];
     // wave-uniform values live in scalar registers, so the loops have scalar
     // control flow
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    x_wave<PREC, RB, DIAG>(a, blockIdx.x * 4 + w, tbuf[w]);
+    // workgroup b runs on XCD b % 8 (round-robin dispatch); it takes logical
+    // workgroup (b % 8) * (grid / 8) + b / 8, so consecutive logical
+    // workgroups, the regions of one channel and split that read the same
+    // records, share an XCD and its L2
+    const int lb = (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+    const int wave = lb * 4 + w;
+    if constexpr (KIND == kBoth) {
+        if (wave % a.nregions < a.n_diag)
+            x_wave<PREC, RB, true>(a, wave, tbuf[w]);
+        else
+            x_wave<PREC, RB, false>(a, wave, tbuf[w]);
+    } else {
+        x_wave<PREC, RB, KIND == kDiag>(a, wave, tbuf[w]);
+    }
 }
 
-template <int PREC, int RB, bool DIAG>
+template <int PREC, int RB, int KIND>
 hipError_t launch_one(const XArgs &a, hipStream_t st) {
     const int64_t waves = (int64_t)a.nregions * a.K * a.nsplit;
-    const int grid = (int)((waves + 3) / 4);
-    hipLaunchKernelGGL((xstage_kernel<PREC, RB, DIAG>), dim3(grid), dim3(256), 0, st, a);
+    const int grid = (int)(8 * ((waves + 31) / 32));  // a multiple of 8; waves past the end exit
+    hipLaunchKernelGGL((xstage_kernel<PREC, RB, KIND>), dim3(grid), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
 template <int PREC>
-hipError_t launch_p(int rb, int diag, const XArgs &a, hipStream_t st) {
-    if (diag) {
+hipError_t launch_p(int rb, int kind, const XArgs &a, hipStream_t st) {
+    if (kind == kDiag) {
         switch (rb) {
-            case 1: return launch_one<PREC, 1, true>(a, st);
-            case 2: return launch_one<PREC, 2, true>(a, st);
-            case 3: return launch_one<PREC, 3, true>(a, st);
-            case 4: return launch_one<PREC, 4, true>(a, st);
-            case 5: return launch_one<PREC, 5, true>(a, st);
-            case 6: return launch_one<PREC, 6, true>(a, st);
+            case 1: return launch_one<PREC, 1, kDiag>(a, st);
+            case 2: return launch_one<PREC, 2, kDiag>(a, st);
+            case 3: return launch_one<PREC, 3, kDiag>(a, st);
+            case 4: return launch_one<PREC, 4, kDiag>(a, st);
+            case 5: return launch_one<PREC, 5, kDiag>(a, st);
+            case 6: return launch_one<PREC, 6, kDiag>(a, st);
         }
-    } else {
+    } else if (kind == kOffDiag) {
         switch (rb) {
-            case 2: return launch_one<PREC, 2, false>(a, st);
-            case 3: return launch_one<PREC, 3, false>(a, st);
-            case 4: return launch_one<PREC, 4, false>(a, st);
+            case 2: return launch_one<PREC, 2, kOffDiag>(a, st);
+            case 3: return launch_one<PREC, 3, kOffDiag>(a, st);
+            case 4: return launch_one<PREC, 4, kOffDiag>(a, st);
+        }
+    } else if (kind == kBoth) {
+        switch (rb) {
+            case 2: return launch_one<PREC, 2, kBoth>(a, st);
+            case 3: return launch_one<PREC, 3, kBoth>(a, st);
+            case 4: return launch_one<PREC, 4, kBoth>(a, st);
         }
     }
     return hipErrorInvalidValue;
@@ -54,11 +78,11 @@ hipError_t launch_p(int rb, int diag, const XArgs &a, hipStream_t st) {
 
 }  // namespace
 
-hipError_t launch_xstage(int prec, int rb, int diag, const XArgs &a, hipStream_t st) {
+hipError_t launch_xstage(int prec, int rb, int kind, const XArgs &a, hipStream_t st) {
     switch (prec) {
-        case kFP32: return launch_p<kFP32>(rb, diag, a, st);
-        case kFP16: return launch_p<kFP16>(rb, diag, a, st);
-        case kINT8: return launch_p<kINT8>(rb, diag, a, st);
+        case kFP32: return launch_p<kFP32>(rb, kind, a, st);
+        case kFP16: return launch_p<kFP16>(rb, kind, a, st);
+        case kINT8: return launch_p<kINT8>(rb, kind, a, st);
     }
     return hipErrorInvalidValue;
 }
