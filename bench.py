@@ -302,7 +302,7 @@ def main():
         per_launch_ms = st["x"] / max(1, launches["x"])
         flops = metrics.x_ops(N_ANT, K, chunk)
         achieved = flops / (per_launch_ms * 1e-3) / 1e12
-        t = measured_traffic("xstage_kernel<0, 3, true>", chunk)
+        t = measured_traffic("xstage_kernel<0, 3, 1>", chunk)
         roof = {"kernel": "xstage_kernel (fp32 MFMA, Hermitian rank-T update)", "bound": "mfma",
                 "achieved": round(achieved, 2), "peak": PEAK["fp32_tflops"], "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK["fp32_tflops"], 4), "traffic": t,
