@@ -108,9 +108,10 @@ def test_fp32_end_to_end(N, K, S):
         assert np.all(raw[bl, :, 1] == 0.0) and np.all(raw[bl, :, 0] >= 0.0)
 
 
-def test_fp32_large_n_regions():
-    """N = 256 uses the multi-region X-stage (diagonal and off-diagonal)."""
-    N, K, S = 256, 512, 24
+@pytest.mark.parametrize("N,K,S", [(256, 512, 24), (160, 128, 40)])
+def test_fp32_large_n_regions(N, K, S):
+    """N above 96 uses the multi-region X-stage (diagonal and off-diagonal
+    launches); N = 160 pads to 192 antennas."""
     print(f"\n[fp32 large N] N={N} K={K} S={S}", flush=True)
     r = synth.recipe_sources(N=N, two_k=2 * K, seed=4)
     packed = _packed(r, S)
@@ -203,9 +204,10 @@ def test_int8_bit_exact_on_gpu_spectra(N, K, S):
     assert np.mean(diff != 0) <= 1e-3
 
 
-@pytest.mark.parametrize("N,K,S", [(44, 256, 200), (64, 128, 33), (256, 256, 16)])
+@pytest.mark.parametrize("N,K,S", [(44, 256, 200), (64, 128, 33), (256, 256, 16), (160, 128, 24)])
 def test_int8_x_stage_on_oracle_spectra(N, K, S):
-    """Oracle-quantised spectra through corr_process_spectra: bit-exact."""
+    """Oracle-quantised spectra through corr_process_spectra: bit-exact.
+    N = 256 and N = 160 (padded to 192) run both region kinds in one launch."""
     rng = np.random.default_rng(N * K + S)
     q = rng.integers(-127, 128, (S, N, K, 2)).astype(np.int8)
     q[:, :, :, :][rng.random((S, N, K, 2)) < 0.01] = 127
@@ -295,8 +297,10 @@ def test_fp16_matches_oracle(N, K, S):
     assert coef_error(raw, ref, N) <= TOL[corr.CORR_FP16]
 
 
-def test_fp16_x_stage_on_oracle_spectra():
-    N, K, S = 44, 256, 96
+@pytest.mark.parametrize("N,K,S", [(44, 256, 96), (160, 128, 24)])
+def test_fp16_x_stage_on_oracle_spectra(N, K, S):
+    """Half spectra through corr_process_spectra against float64 on the same
+    values; N = 160 runs both region kinds in one launch."""
     rng = np.random.default_rng(2)
     spec = (rng.standard_normal((S, N, K)) * 50 + 1j * rng.standard_normal((S, N, K)) * 50)
     half = spec.real.astype(np.float16).astype(np.float64) + 1j * spec.imag.astype(np.float16).astype(np.float64)
