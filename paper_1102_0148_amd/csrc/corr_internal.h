@@ -74,6 +74,18 @@ int fstage_lds_bytes(int M, int prec, int ga);
 int fstage_default_group(int M, int prec);
 
 // ---------------------------------------------------------------- X-stage
+// A group of X regions that share their antenna blocks (large N, regions of
+// 4 x 4 blocks): the blocks of rows [r0, r0 + 8) and columns [c0, c0 + 8)
+// (the same range when diag) are staged in LDS once per k-block for all of
+// the group's regions, one region per wave.
+struct XGroup {
+    int r0, c0;          // first block of the row range and of the column range
+    int diag;            // 1: column range = row range (8 blocks staged), 0: 16
+    int nreg;            // regions in the group (3 or 4)
+    int2 reg[4];         // (I0, J0) block coordinates of each region
+    int kind[4];         // 1: diagonal region (upper triangle), 0: off-diagonal
+};
+
 struct XArgs {
     const uint4 *spec;   // records, index rec_index(c, tq, a, K, a_pad)
     void *partial;       // [nsplit][K][nb] float2 (fp32/fp16) or int2 (int8)
@@ -83,11 +95,16 @@ struct XArgs {
     int N, a_pad, K, ntq, nb;
     int nsplit;
     int nkb;             // k-blocks in the chunk = ntq / 4
+    const XGroup *groups; // group launches: the region groups of a channel
+    int ngroups;
 };
 // rb: region side in 16-antenna blocks; kind 1: regions on the diagonal
 // (upper-triangle pairs only), 0: off the diagonal (full rb x rb), 2: both,
 // the first a.n_diag regions diagonal (rb 2..4).
 hipError_t launch_xstage(int prec, int rb, int kind, const XArgs &a, hipStream_t st);
+// int8 / fp16 with 4 x 4-block regions: one workgroup per (group, channel,
+// split), the group's blocks staged through an LDS ring (a.groups).
+hipError_t launch_xgroups(int prec, const XArgs &a, hipStream_t st);
 
 // ---------------------------------------------------------------- dump etc.
 // acc[f][bl] (double2) += sum over splits of partial[sp][f][bl], in split order.

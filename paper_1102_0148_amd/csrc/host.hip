@@ -110,6 +110,8 @@ struct corr_ctx {
     bool planned = false, started = false;
     int TG = 2, ntq_buf = 0;
     int nblk = 0, rb = 0, n_diag = 0, n_off = 0;
+    XGroup *xgroups = nullptr;  // region groups for LDS-staged int8 / fp16 (large N)
+    int n_xgroups = 0;
     // device buffers
     uint4 *spec = nullptr;
     size_t spec_bytes = 0;
@@ -169,7 +171,7 @@ void free_ctx(corr_ctx *h) {
     if (h->graph) hipGraphDestroy(h->graph);
     if (h->cap_stream) hipStreamDestroy(h->cap_stream);
     void *bufs[] = {h->spec,   h->partial, h->acc,   h->stage,   h->tw,   h->scales, h->power,
-                    h->regions, h->sat, h->fticket, h->bjobs, h->in_ptrs, h->items, h->bctr};
+                    h->regions, h->sat, h->fticket, h->xgroups, h->bjobs, h->in_ptrs, h->items, h->bctr};
     for (void *p : bufs)
         if (p) hipFree(p);
     for (corr_ctx *j : h->jobs) free_ctx(j);
@@ -270,7 +272,7 @@ int timers_collect(corr_ctx *h) {
 }
 
 int launch_x_and_dump(corr_ctx *h, const uint4 *spec, int ntq, int nkb, hipStream_t st) {
-    XArgs xa;
+    XArgs xa{};
     xa.spec = spec;
     xa.partial = h->partial;
     xa.N = h->N;
@@ -283,7 +285,13 @@ int launch_x_and_dump(corr_ctx *h, const uint4 *spec, int ntq, int nkb, hipStrea
     timer_begin(h, 2, st);
     xa.regions = h->regions;
     xa.n_diag = h->n_diag;
-    if (h->n_off && h->prec != kFP32) {
+    if (h->n_xgroups && h->prec != kFP32) {
+        // groups of regions that share blocks stage them in LDS once per
+        // k-block, with the loads two k-blocks ahead
+        xa.groups = h->xgroups;
+        xa.ngroups = h->n_xgroups;
+        HIP_TRY(launch_xgroups(h->prec, xa, st), "X-stage launch");
+    } else if (h->n_off && h->prec != kFP32) {
         // one launch over every region of a channel (diagonal ones first), so
         // the regions that share records read them from HBM once, through one
         // L2: the int8 and fp16 forms are bound by that traffic
@@ -425,6 +433,45 @@ hipError_t set_regions(corr_ctx *h, int rb) {
     h->rb = rb;
     h->n_diag = n_diag;
     h->n_off = (int)regs.size() - n_diag;
+    // Region groups sharing their blocks, for 4 x 4-block regions in an even
+    // number of region rows: region rows 2i and 2i+1 give a diagonal group
+    // (two diagonal regions and the off-diagonal one between them, 8 blocks)
+    // and, with region columns 2j and 2j+1 (j > i), an off-diagonal group of
+    // four regions (16 blocks).  Together they tile the triangle.
+    if (h->xgroups) hipFree(h->xgroups);
+    h->xgroups = nullptr;
+    h->n_xgroups = 0;
+    if (rb == 4 && nr >= 2 && nr % 2 == 0) {
+        std::vector<XGroup> gs;
+        for (int i = 0; i < nr; i += 2) {
+            XGroup d{};
+            d.r0 = d.c0 = 4 * i;
+            d.diag = 1;
+            d.nreg = 3;
+            d.reg[0] = make_int2(4 * i, 4 * i);
+            d.kind[0] = 1;
+            d.reg[1] = make_int2(4 * i, 4 * i + 4);
+            d.kind[1] = 0;
+            d.reg[2] = make_int2(4 * i + 4, 4 * i + 4);
+            d.kind[2] = 1;
+            gs.push_back(d);
+            for (int j = i + 2; j < nr; j += 2) {
+                XGroup o{};
+                o.r0 = 4 * i;
+                o.c0 = 4 * j;
+                o.nreg = 4;
+                for (int k = 0; k < 4; ++k) {
+                    o.reg[k] = make_int2(4 * i + 4 * (k / 2), 4 * j + 4 * (k % 2));
+                    o.kind[k] = 0;
+                }
+                gs.push_back(o);
+            }
+        }
+        if ((e = hipMalloc(&h->xgroups, gs.size() * sizeof(XGroup))) != hipSuccess) return e;
+        if ((e = hipMemcpy(h->xgroups, gs.data(), gs.size() * sizeof(XGroup), hipMemcpyHostToDevice)) != hipSuccess)
+            return e;
+        h->n_xgroups = (int)gs.size();
+    }
     return hipSuccess;
 }
 

@@ -76,7 +76,53 @@ hipError_t launch_p(int rb, int kind, const XArgs &a, hipStream_t st) {
     return hipErrorInvalidValue;
 }
 
+// Region groups through a 3-stage LDS ring (3 x 16 KB); two workgroups per
+// CU keep the 4 x 4-block accumulators in VGPRs.  The three stages are
+// separate arrays so the compiler can tell a stage being read from the stage
+// that a direct load is filling, and adds no wait between them.
+template <int PREC>
+__global__ __launch_bounds__(256, 2) void xgroup_kernel(XArgs a) {
+    // one array per stage: the compiler then tells the stages apart and waits
+    // for a stage's own loads only, not for every load to LDS in flight
+    __shared__ __attribute__((aligned(16))) uint4 st0[kXStage];
+    __shared__ __attribute__((aligned(16))) uint4 st1[kXStage];
+    __shared__ __attribute__((aligned(16))) uint4 st2[kXStage];
+#if X_RING >= 4
+    __shared__ __attribute__((aligned(16))) uint4 st3[kXStage];
+#endif
+#if X_RING >= 5
+    __shared__ __attribute__((aligned(16))) uint4 st4[kXStage];
+#endif
+    uint4 *const st[kXRing] = {st0, st1, st2
+#if X_RING >= 4
+                               , st3
+#endif
+#if X_RING >= 5
+                               , st4
+#endif
+    };
+    // logical workgroup as in xstage_kernel: a channel's groups share an XCD
+    const int lb = (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+    x_group<PREC>(a, lb, st);
+}
+
+template <int PREC>
+hipError_t launch_group(const XArgs &a, hipStream_t st) {
+    const int64_t units = (int64_t)a.ngroups * a.K * a.nsplit;
+    const int grid = (int)(8 * ((units + 7) / 8));  // a multiple of 8; units past the end exit
+    hipLaunchKernelGGL((xgroup_kernel<PREC>), dim3(grid), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_xgroups(int prec, const XArgs &a, hipStream_t st) {
+    switch (prec) {
+        case kFP16: return launch_group<kFP16>(a, st);
+        case kINT8: return launch_group<kINT8>(a, st);
+    }
+    return hipErrorInvalidValue;
+}
 
 hipError_t launch_xstage(int prec, int rb, int kind, const XArgs &a, hipStream_t st) {
     switch (prec) {

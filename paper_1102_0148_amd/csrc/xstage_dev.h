@@ -240,5 +240,176 @@ __device__ __forceinline__ void x_wave(const XArgs &a, int wave, float *tb) {
         }
 }
 
+// ------------------------------------------------------------ LDS groups
+// A stage of the LDS ring: 16 block slots of one k-block, slot s holding
+// [record g][antenna r] (16 B each) of block r0 + s (s < 8) or c0 + s - 8.
+constexpr int kXSlots = 16;
+constexpr int kXStage = kXSlots * 64;  // uint4 per stage (16 KB)
+#ifndef X_RING
+#define X_RING 3
+#endif
+constexpr int kXRing = X_RING;  // stages in the ring
+
+// Issue this wave's share of one k-block's blocks as direct global-to-LDS
+// loads (16 B per lane; lane l lands at slot base + 16 l, which is the
+// [g][r] order, lane = 16 g + r).  NS slots per k-block, NS / 4 per wave.
+template <int NS>
+__device__ __forceinline__ void xg_issue(const uint4 *spec, int K, int a_pad, int r0, int c0, int f, int kb,
+                                         uint4 *stage, int wave) {
+    const int lane = threadIdx.x & 63;
+    const uint4 *rec = spec + ((int64_t)(kb >> 2) * K + f) * kTQB * a_pad + (kb & 3) * 4 * a_pad +
+                       (lane >> 4) * a_pad + (lane & 15);
+#pragma unroll
+    for (int i = 0; i < NS / 4; ++i) {
+        const int s = wave * (NS / 4) + i;
+        const int blk = s < 8 ? r0 + s : c0 + (s - 8);
+        __builtin_amdgcn_global_load_lds(rec + blk * 16, stage + s * 64, 16, 0, 0);
+    }
+}
+
+// One k-block of a region from a stage: P/Q products as in x_wave.
+template <int PREC, bool DIAG>
+__device__ __forceinline__ void xg_compute(const uint4 *stage, int rs, int cs,
+                                           typename AccT<PREC>::type (&accR)[4][4],
+                                           typename AccT<PREC>::type (&accI)[4][4]) {
+    const int lane = threadIdx.x & 63;
+    uint4 pr[4], pc[4], qr[4];
+#pragma unroll
+    for (int I = 0; I < 4; ++I) pr[I] = stage[(rs + I) * 64 + lane];
+    if constexpr (!DIAG) {
+#pragma unroll
+        for (int J = 0; J < 4; ++J) pc[J] = stage[(cs + J) * 64 + lane];
+    }
+#pragma unroll
+    for (int I = 0; I < 4; ++I) qr[I] = make_q<PREC>(pr[I]);
+#pragma unroll
+    for (int I = 0; I < 4; ++I)
+#pragma unroll
+        for (int J = 0; J < 4; ++J) {
+            if (DIAG && J < I) continue;
+            const uint4 b = DIAG ? pr[J] : pc[J];
+            mma<PREC>(accR[I][J], pr[I], b);
+            mma<PREC>(accI[I][J], qr[I], b);
+        }
+}
+
+// s_waitcnt vmcnt(n) lgkmcnt(0), expcnt left alone.  The builtin takes an
+// immediate only; n is a constant after unrolling and the switch folds away
+// (a count above 15 waits for everything, which is never wrong).
+__device__ __forceinline__ void wait_vm_lgkm0(int n) {
+    switch (n) {
+#define X_WAIT_CASE(c) \
+    case c: __builtin_amdgcn_s_waitcnt(0x0070 | c); break;
+        X_WAIT_CASE(1) X_WAIT_CASE(2) X_WAIT_CASE(3) X_WAIT_CASE(4) X_WAIT_CASE(5) X_WAIT_CASE(6)
+        X_WAIT_CASE(7) X_WAIT_CASE(8) X_WAIT_CASE(9) X_WAIT_CASE(10) X_WAIT_CASE(11) X_WAIT_CASE(12)
+        X_WAIT_CASE(13) X_WAIT_CASE(14) X_WAIT_CASE(15)
+#undef X_WAIT_CASE
+        default: __builtin_amdgcn_s_waitcnt(0x0070); break;
+    }
+}
+
+// The k-block loop of one wave's region over a ring of kXRing stages: the
+// loads run kXRing - 1 k-blocks ahead, and one barrier per k-block both
+// publishes the stage about to be used and frees the one about to be
+// refilled.  Each wave waits only for its own loads of the current k-block
+// (vmcnt), then the barrier covers every wave's; lgkmcnt(0) first retires
+// this wave's reads of the stage that the loads issued after the barrier
+// overwrite.  (A __syncthreads here would wait for every load in flight, the
+// prefetch too.)  Whole rounds of kXRing k-blocks come first, so every path
+// into a round has the same loads in flight, which keeps the compiler's own
+// vmcnt bookkeeping exact; the last k-blocks, fewer than kXRing, already sit
+// in the first stages.  Loads past the range repeat the last k-block.
+template <int PREC, bool DIAG, int NS>
+__device__ __forceinline__ void xg_loop(const uint4 *spec, int K, int a_pad, int r0, int c0, int f, int kb0,
+                                        int kb1, int wave, int rs, int cs, bool active,
+                                        uint4 *const (&st)[kXRing], typename AccT<PREC>::type (&accR)[4][4],
+                                        typename AccT<PREC>::type (&accI)[4][4]) {
+    constexpr int kPer = NS / 4;  // loads per wave per k-block
+    const int last = kb1 - 1;
+#pragma unroll
+    for (int s = 0; s + 1 < kXRing; ++s) xg_issue<NS>(spec, K, a_pad, r0, c0, f, min(kb0 + s, last), st[s], wave);
+    int kb = kb0;
+#pragma unroll 1
+    for (; kb + kXRing <= kb1; kb += kXRing) {
+#pragma unroll
+        for (int s = 0; s < kXRing; ++s) {
+            wait_vm_lgkm0((kXRing - 2) * kPer);
+            __builtin_amdgcn_s_barrier();
+            xg_issue<NS>(spec, K, a_pad, r0, c0, f, min(kb + s + kXRing - 1, last), st[(s + kXRing - 1) % kXRing],
+                         wave);
+            if (active) xg_compute<PREC, DIAG>(st[s], rs, cs, accR, accI);
+        }
+    }
+#pragma unroll
+    for (int s = 0; s + 1 < kXRing; ++s) {
+        if (kb + s < kb1) {
+            wait_vm_lgkm0((kXRing - 2 - s) * kPer);
+            __builtin_amdgcn_s_barrier();
+            if (active) xg_compute<PREC, DIAG>(st[s], rs, cs, accR, accI);
+        }
+    }
+    wait_vm_lgkm0(0);  // the ring's last loads have landed
+}
+
+// A workgroup's share of the X-stage with LDS-staged groups: unit = group
+// (fastest), channel, split.  Wave w takes the group's region w.  int8 and
+// fp16 (P / Q form) only.
+template <int PREC>
+__device__ __forceinline__ void x_group(const XArgs &a, int unit, uint4 *const (&st)[kXRing]) {
+    typedef typename AccT<PREC>::type acc_t;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (unit >= a.ngroups * a.K * a.nsplit) return;  // the whole workgroup
+    const XGroup &gr = a.groups[unit % a.ngroups];
+    const int rest = unit / a.ngroups;
+    const int f = rest % a.K;
+    const int sp = rest / a.K;
+    const int kb0 = (int)((int64_t)sp * a.nkb / a.nsplit);
+    const int kb1 = (int)((int64_t)(sp + 1) * a.nkb / a.nsplit);
+    // the group's fields once, into registers (read inside the loop they would
+    // be loads the k-block waits would have to cover)
+    const int r0 = gr.r0, c0 = gr.c0, gdiag = gr.diag;
+    const bool active = wave < gr.nreg;
+    const int I0 = active ? gr.reg[wave].x : 0, J0 = active ? gr.reg[wave].y : 0;
+    const bool dreg = active && gr.kind[wave];
+    const int rs = I0 - r0;
+    const int cs = gdiag ? J0 - r0 : 8 + (J0 - c0);
+    const uint4 *spec = a.spec;
+    const int K = a.K, a_pad = a.a_pad;
+    acc_t accR[4][4], accI[4][4];
+#pragma unroll
+    for (int I = 0; I < 4; ++I)
+#pragma unroll
+        for (int J = 0; J < 4; ++J) accR[I][J] = accI[I][J] = acc_t{0, 0, 0, 0};
+    if (kb0 < kb1) {
+        if (gdiag) {
+            if (dreg)
+                xg_loop<PREC, true, 8>(spec, K, a_pad, r0, c0, f, kb0, kb1, wave, rs, cs, active, st, accR, accI);
+            else
+                xg_loop<PREC, false, 8>(spec, K, a_pad, r0, c0, f, kb0, kb1, wave, rs, cs, active, st, accR, accI);
+        } else {
+            xg_loop<PREC, false, 16>(spec, K, a_pad, r0, c0, f, kb0, kb1, wave, rs, cs, active, st, accR, accI);
+        }
+    }
+    if (!active) return;
+    // accumulator element v of lane l is row 4*(l/16)+v, column l%16
+    const int64_t obase = ((int64_t)sp * a.K + f) * a.nb;
+#pragma unroll
+    for (int I = 0; I < 4; ++I)
+#pragma unroll
+        for (int J = 0; J < 4; ++J) {
+            if (dreg && J < I) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int ia = (I0 + I) * 16 + 4 * (lane >> 4) + v;
+                const int ib = (J0 + J) * 16 + (lane & 15);
+                if (ia < a.N && ib < a.N && ia <= ib) {
+                    const int bl = ia * a.N - ia * (ia - 1) / 2 + (ib - ia);
+                    store_vis<PREC>(a.partial, obase + bl, accR[I][J], accI[I][J], v, ia == ib);
+                }
+            }
+        }
+}
+
 }  // namespace
 }  // namespace corr

@@ -204,15 +204,19 @@ def test_int8_bit_exact_on_gpu_spectra(N, K, S):
     assert np.mean(diff != 0) <= 1e-3
 
 
-@pytest.mark.parametrize("N,K,S", [(44, 256, 200), (64, 128, 33), (256, 256, 16), (160, 128, 24)])
-def test_int8_x_stage_on_oracle_spectra(N, K, S):
+@pytest.mark.parametrize("N,K,S,splits", [(44, 256, 200, 0), (64, 128, 33, 0), (256, 256, 16, 0),
+                                          (160, 128, 24, 0), (256, 128, 200, 1), (256, 128, 200, 3),
+                                          (200, 128, 136, 2)])
+def test_int8_x_stage_on_oracle_spectra(N, K, S, splits):
     """Oracle-quantised spectra through corr_process_spectra: bit-exact.
-    N = 256 and N = 160 (padded to 192) run both region kinds in one launch."""
+    N = 160 (padded to 192) runs both region kinds in one launch; N = 256 and
+    N = 200 (padded to 256) run the LDS-staged region groups, over k-block
+    ranges that are whole rounds of the ring and ragged ones."""
     rng = np.random.default_rng(N * K + S)
     q = rng.integers(-127, 128, (S, N, K, 2)).astype(np.int8)
     q[:, :, :, :][rng.random((S, N, K, 2)) < 0.01] = 127
     buf = torch.from_numpy(corr.spectra_to_records(q, corr.CORR_INT8)).cuda()
-    c = corr.Correlator(N, K, S, precision="int8")
+    c = corr.Correlator(N, K, S, precision="int8", tiles=dict(x_splits=splits) if splits else None)
     c.process_spectra(buf, S)
     raw = c.read_cps_raw()
     np.testing.assert_array_equal(raw, oracle.cmac_i64(q).astype(np.float64))
@@ -297,10 +301,11 @@ def test_fp16_matches_oracle(N, K, S):
     assert coef_error(raw, ref, N) <= TOL[corr.CORR_FP16]
 
 
-@pytest.mark.parametrize("N,K,S", [(44, 256, 96), (160, 128, 24)])
+@pytest.mark.parametrize("N,K,S", [(44, 256, 96), (160, 128, 24), (256, 128, 100), (220, 128, 52)])
 def test_fp16_x_stage_on_oracle_spectra(N, K, S):
     """Half spectra through corr_process_spectra against float64 on the same
-    values; N = 160 runs both region kinds in one launch."""
+    values; N = 160 runs both region kinds in one launch, N = 256 and N = 220
+    (padded to 256) the LDS-staged region groups."""
     rng = np.random.default_rng(2)
     spec = (rng.standard_normal((S, N, K)) * 50 + 1j * rng.standard_normal((S, N, K)) * 50)
     half = spec.real.astype(np.float16).astype(np.float64) + 1j * spec.imag.astype(np.float16).astype(np.float64)
