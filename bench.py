@@ -163,8 +163,9 @@ def large_n(corr, torch, metrics, steps, warmup):
 
 def batch(corr, torch, metrics, steps, warmup):
     """12 uneven jobs, (N, FFT size) drawn from the paper-scale set, 16384
-    spectra each, rho ~ U[0, 0.1]: one persistent launch replayed from a HIP
-    graph, all-int8 and all-fp32."""
+    spectra each, rho ~ U[0, 0.1], all-int8 and all-fp32, replayed from one HIP
+    graph in both batch modes (each job's kernels on parallel branches; one
+    persistent kernel), against the same jobs as separate correlators."""
     import synth
     recipes = synth.batch_jobs(12, seed=3)
     S = 16384
@@ -172,8 +173,8 @@ def batch(corr, torch, metrics, steps, warmup):
     a_s = sum(metrics.antenna_samples(r.N, r.two_k, S) for r in recipes)
     out = {"workload": "12 jobs, (N, 2K) drawn from " + ", ".join(f"({n},{k})" for n, k in synth.BATCH_SHAPES)
            + f", {S} spectra each", "jobs": [[r.N, r.two_k] for r in recipes]}
-    for prec in ("fp32", "int8"):
-        b = corr.Batch([(r.N, r.K, S, prec) for r in recipes], tiles="auto")
+    def time_batch(prec, mode):
+        b = corr.Batch([(r.N, r.K, S, prec) for r in recipes], tiles="auto", mode=mode)
         for _ in range(warmup):
             b.process(xs)
             for j in range(len(recipes)):
@@ -189,8 +190,12 @@ def batch(corr, torch, metrics, steps, warmup):
             times.append(e0.elapsed_time(e1))
             for j in range(len(recipes)):
                 b.read_cps_raw(j)
-        ms = sorted(times)[len(times) // 2]
         b.close()
+        return sorted(times)[len(times) // 2]
+
+    for prec in ("fp32", "int8"):
+        ms = time_batch(prec, "branches")
+        ms_pers = time_batch(prec, "persistent")
         # the same jobs as separate single-job correlators, one after another on
         # one stream (reads outside the timed region, as for the batch)
         cs = [corr.Correlator(r.N, r.K, S, precision=prec, tiles="auto") for r in recipes]
@@ -210,9 +215,11 @@ def batch(corr, torch, metrics, steps, warmup):
         for c in cs:
             c.close()
         ms_sep = sorted(sep)[len(sep) // 2]
-        out[prec] = {"antenna_msps": round(a_s / (ms * 1e-3) / 1e6, 1), "ms_per_batch": round(ms, 4),
-                     "separate_launches_ms": round(ms_sep, 4),
-                     "batch_speedup_vs_separate": round(ms_sep / ms, 3)}
+        out[prec] = {"antenna_msps": round(a_s / (ms * 1e-3) / 1e6, 1), "mode": "branches",
+                     "ms_per_batch": round(ms, 4), "separate_launches_ms": round(ms_sep, 4),
+                     "batch_speedup_vs_separate": round(ms_sep / ms, 3),
+                     "persistent_ms_per_batch": round(ms_pers, 4),
+                     "persistent_speedup_vs_separate": round(ms_sep / ms_pers, 3)}
         log(f"[bench] batch {prec}: {out[prec]}")
     del xs
     torch.cuda.empty_cache()

@@ -164,11 +164,18 @@ void corr_destroy(corr_handle h);
 const char *corr_last_error(void);
 
 /* ----------------------------------------------------------------- batch
- * Many independent correlations of different N and K run as one persistent
- * kernel launch, replayed as a captured HIP graph (no counterpart in the
+ * Many independent correlations of different N and K run from one captured
+ * HIP graph, replayed by each corr_batch_process (no counterpart in the
  * paper; the closest is Section 3.1's replication of core pairs to absorb
  * more elements or bandwidth).  Each job follows the single-job semantics
- * above.  */
+ * above.  Two ways to run the jobs (corr_batch_set_mode):
+ *   CORR_BATCH_BRANCHES   (default) each job's own F-stage, X-stage and dump
+ *                         kernels, the jobs spread over four parallel branches
+ *                         of the graph;
+ *   CORR_BATCH_PERSISTENT one persistent kernel over an ordered work list of
+ *                         every job's F, X and dump items (one launch). */
+#define CORR_BATCH_BRANCHES 0
+#define CORR_BATCH_PERSISTENT 1
 typedef struct {
     int N;
     int K;
@@ -180,7 +187,14 @@ typedef struct {
  * Tile choices come from the autotuner's table (corr_batch_set_tiles), else
  * defaults.  NULL on error.  */
 corr_handle corr_batch_create(const corr_job *jobs, int n_jobs);
+/* Tiles of one job: chunk_spectra must be 0 or the whole job rounded up to
+ * 64 (a batch job is one chunk), f_group 0 or the default for its K and
+ * precision; x_splits is free.  Before the first corr_batch_process only. */
 int corr_batch_set_tiles(corr_handle b, int job, const corr_tiles *t);
+/* mode: CORR_BATCH_BRANCHES or CORR_BATCH_PERSISTENT.  Before the first
+ * corr_batch_process only (CORR_ESTATE after), CORR_EINVAL for another
+ * value.  Both modes give the same results as the single-job path. */
+int corr_batch_set_mode(corr_handle b, int mode);
 /* packed_per_job: HOST array of n_jobs DEVICE pointers, job j's frames as in
  * corr_process.  Enqueues one graph launch on `stream`.  */
 int corr_batch_process(corr_handle b, const void *const *packed_per_job, void *stream);

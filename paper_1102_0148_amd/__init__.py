@@ -25,6 +25,8 @@ CORR_OK, CORR_EINVAL, CORR_ENOMEM, CORR_EHIP, CORR_ESTATE = 0, -1, -2, -3, -4
 CORR_FP32, CORR_FP16, CORR_INT8 = 0, 1, 2
 CORR_CALIB_SPECTRA = 1024
 PRECISIONS = {"fp32": CORR_FP32, "fp16": CORR_FP16, "int8": CORR_INT8}
+CORR_BATCH_BRANCHES, CORR_BATCH_PERSISTENT = 0, 1
+BATCH_MODES = {"branches": CORR_BATCH_BRANCHES, "persistent": CORR_BATCH_PERSISTENT}
 
 # Every symbol include/corr.h declares.
 EXPORTS = (
@@ -32,7 +34,7 @@ EXPORTS = (
     "corr_read_cps", "corr_read_cps_raw", "corr_read_cps_async", "corr_read_scales",
     "corr_spectra_bytes", "corr_process_spectra", "corr_debug_read_spectra", "corr_get_stats",
     "corr_enable_timing", "corr_destroy", "corr_last_error", "corr_batch_create",
-    "corr_batch_set_tiles", "corr_batch_process", "corr_batch_read_cps",
+    "corr_batch_set_tiles", "corr_batch_set_mode", "corr_batch_process", "corr_batch_read_cps",
     "corr_batch_read_cps_raw", "corr_batch_read_scales",
 )
 
@@ -93,6 +95,7 @@ def load(path: str = LIB_PATH):
         "corr_last_error": (ctypes.c_char_p, []),
         "corr_batch_create": (P, [ctypes.POINTER(corr_job), I]),
         "corr_batch_set_tiles": (I, [P, I, ctypes.POINTER(corr_tiles)]),
+        "corr_batch_set_mode": (I, [P, I]),
         "corr_batch_process": (I, [P, ctypes.POINTER(P), P]),
         "corr_batch_read_cps": (I, [P, I, P]),
         "corr_batch_read_cps_raw": (I, [P, I, P]),
@@ -200,6 +203,10 @@ def corr_batch_create(jobs):
 def corr_batch_set_tiles(b, job: int, chunk_spectra=0, x_splits=0, f_group=0):
     t = corr_tiles(chunk_spectra, x_splits, f_group)
     return _check(load().corr_batch_set_tiles(b, job, ctypes.byref(t)))
+
+
+def corr_batch_set_mode(b, mode: int):
+    return _check(load().corr_batch_set_mode(b, mode))
 
 
 def corr_batch_process(b, packed_ptrs, stream: int = 0):
@@ -377,23 +384,29 @@ def records_to_spectra(buf: np.ndarray, precision: int, N: int, K: int, S: int) 
 
 
 class Batch:
-    """Many correlations of different shapes in one persistent kernel launch,
-    replayed from a captured HIP graph.  jobs: list of (N, K, n_spectra,
-    precision); tiles: optional {job index: {"x_splits": s}}."""
+    """Many correlations of different shapes replayed from one captured HIP
+    graph: each job's own kernels on parallel branches ("branches", the
+    default) or one persistent kernel over every job ("persistent").
+    jobs: list of (N, K, n_spectra, precision); tiles: "auto" (the
+    autotuner's table) or {job index: {"x_splits": s}}."""
 
-    def __init__(self, jobs, tiles=None):
+    def __init__(self, jobs, tiles=None, mode="branches"):
         self.jobs = [(int(N), int(K), int(S), PRECISIONS[p] if isinstance(p, str) else int(p))
                      for (N, K, S, p) in jobs]
+        self.mode = BATCH_MODES[mode] if isinstance(mode, str) else int(mode)
         self.h = corr_batch_create(self.jobs)
         if isinstance(tiles, str) and tiles == "auto":
             from . import tune
             names = {v: k for k, v in PRECISIONS.items()}
             tiles = {}
             for j, (N, K, S, p) in enumerate(self.jobs):
-                found = tune.lookup(N, K, S, names[p], batch=True)
+                # the persistent kernel has its own table entries; branches
+                # run the single-job kernels
+                found = tune.lookup(N, K, S, names[p], batch=self.mode == CORR_BATCH_PERSISTENT)
                 if found:
                     tiles[j] = {"x_splits": found["x_splits"]}
         try:
+            corr_batch_set_mode(self.h, self.mode)
             for j, t in (tiles or {}).items():
                 corr_batch_set_tiles(self.h, j, **t)
         except Exception:

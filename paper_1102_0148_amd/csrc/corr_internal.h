@@ -44,6 +44,7 @@ inline int64_t round_up64(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 // ---------------------------------------------------------------- F-stage
 struct FArgs {
     const uint8_t *in;        // chunk's frames [s][N][M bytes]
+    const uint8_t *const *in_slot;  // if set, `in` is read from here at run time (graph replays)
     uint4 *spec;              // records, index rec_index(c, tq, a, M, a_pad)
     float *power;             // power mode: partial sums [nwg_per_group][a_pad][M]
     const float *scales;      // int8: [N][M]

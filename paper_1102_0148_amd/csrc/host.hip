@@ -124,6 +124,9 @@ struct corr_ctx {
     int2 *regions = nullptr;
     unsigned long long *sat = nullptr;
     unsigned *fticket = nullptr;  // F-stage tile-chunk counters
+    // a job of a branches-mode batch: its input pointer, which the kernels
+    // read from this device slot when the graph replays
+    const uint8_t *const *in_slot = nullptr;
     // state
     int64_t accumulated = 0;
     int last_chunk = 0;
@@ -143,6 +146,10 @@ struct corr_ctx {
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    int bmode = CORR_BATCH_BRANCHES;
+    bool bfailed = false;
+    std::vector<hipStream_t> br_streams;  // branches mode: capture-time side streams
+    std::vector<hipEvent_t> br_events;    // fork, then one join per branch
 };
 
 namespace {
@@ -170,6 +177,8 @@ void free_ctx(corr_ctx *h) {
     if (h->gexec) hipGraphExecDestroy(h->gexec);
     if (h->graph) hipGraphDestroy(h->graph);
     if (h->cap_stream) hipStreamDestroy(h->cap_stream);
+    for (hipStream_t s : h->br_streams) hipStreamDestroy(s);
+    for (hipEvent_t e : h->br_events) hipEventDestroy(e);
     void *bufs[] = {h->spec,   h->partial, h->acc,   h->stage,   h->tw,   h->scales, h->power,
                     h->regions, h->sat, h->fticket, h->xgroups, h->bjobs, h->in_ptrs, h->items, h->bctr};
     for (void *p : bufs)
@@ -320,6 +329,7 @@ int calibrate(corr_ctx *h, const uint8_t *in, hipStream_t st) {
     const int W = std::min(h->S, CORR_CALIB_SPECTRA);
     FArgs fa{};
     fa.in = in;
+    fa.in_slot = h->in_slot;
     fa.power = h->power;
     fa.tw = h->tw;
     fa.N = h->N;
@@ -349,11 +359,13 @@ int process_one(corr_ctx *h, const uint8_t *in, hipStream_t st) {
     const int ga = h->tiles.f_group;
     const int ngroups = (h->N + ga - 1) / ga;
     const int64_t frame = (int64_t)h->N * h->K;
+    if (h->in_slot && chunk < h->S) return fail(CORR_EINVAL, "a job read through an input slot is one chunk");
     for (int c0 = 0; c0 < h->S; c0 += chunk) {
         const int Sc = std::min(chunk, h->S - c0);
         const int ntq_used = round_up((Sc + h->TG - 1) / h->TG, 4);
         FArgs fa{};
-        fa.in = in + (int64_t)c0 * frame;
+        fa.in = h->in_slot ? nullptr : in + (int64_t)c0 * frame;
+        fa.in_slot = h->in_slot;
         fa.spec = h->spec;
         fa.scales = h->scales;
         fa.tw = h->tw;
@@ -748,9 +760,82 @@ int corr_batch_set_tiles(corr_handle b, int job, const corr_tiles *t) {
     return CORR_OK;
 }
 
+int corr_batch_set_mode(corr_handle b, int mode) {
+    if (!b || !b->batch) return fail(CORR_EINVAL, "invalid batch handle");
+    if (mode != CORR_BATCH_BRANCHES && mode != CORR_BATCH_PERSISTENT)
+        return fail(CORR_EINVAL, "batch mode %d is neither CORR_BATCH_BRANCHES nor CORR_BATCH_PERSISTENT", mode);
+    if (b->gexec) return fail(CORR_ESTATE, "the mode is fixed once the batch has run");
+    b->bmode = mode;
+    return CORR_OK;
+}
+
 namespace {
 
-// Plan every job as one chunk, lay out the work list and capture the graph.
+constexpr int kBatchBranches = 4;
+
+// Branches mode: plan every job as one chunk with its own kernels, and
+// capture them into one graph whose jobs run on kBatchBranches parallel
+// branches, dealt round-robin in order of decreasing work.  (Dealing each job
+// to the branch with the least work so far measured slower: it lined the
+// small jobs up behind one another on one branch instead of beside the large
+// ones' tails.)  The kernels read each job's input pointer from b->in_ptrs,
+// which corr_batch_process rewrites before every replay.
+int batch_build_branches(corr_ctx *b) {
+    HIP_TRY(hipSetDevice(b->device), "hipSetDevice");
+    const int nj = (int)b->jobs.size();
+    HIP_TRY(hipMalloc(&b->in_ptrs, nj * sizeof(uint8_t *)), "hipMalloc(batch inputs)");
+    HIP_TRY(hipMemset(b->in_ptrs, 0, nj * sizeof(uint8_t *)), "hipMemset(batch inputs)");
+    std::vector<double> work(nj);
+    for (int j = 0; j < nj; ++j) {
+        corr_ctx *h = b->jobs[j];
+        h->tiles.chunk_spectra = round_up(h->S, 64);
+        h->tiles.f_group = batch_default_group(h->K, h->prec);
+        int rc = plan(h);
+        if (rc) return rc;
+        h->in_slot = b->in_ptrs + j;
+        // F-stage samples plus X-stage complex products
+        work[j] = (double)h->S * h->N * h->K * (2.0 + 0.25 * h->N);
+    }
+    std::vector<int> order(nj);
+    for (int j = 0; j < nj; ++j) order[j] = j;
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
+    const int nbr = std::min(kBatchBranches, nj);
+    HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+    for (int i = 0; i < nbr; ++i) {
+        hipStream_t s = nullptr;
+        HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate");
+        b->br_streams.push_back(s);
+    }
+    for (int i = 0; i <= nbr; ++i) {
+        hipEvent_t e = nullptr;
+        HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+        b->br_events.push_back(e);
+    }
+    HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    // enqueue under capture; the capture ends whatever happens
+    auto enqueue = [&]() -> int {
+        HIP_TRY(hipEventRecord(b->br_events[0], b->cap_stream), "hipEventRecord(fork)");
+        for (hipStream_t s : b->br_streams) HIP_TRY(hipStreamWaitEvent(s, b->br_events[0], 0), "hipStreamWaitEvent");
+        for (int i = 0; i < nj; ++i) {
+            int rc = process_one(b->jobs[order[i]], nullptr, b->br_streams[i % nbr]);
+            if (rc) return rc;
+        }
+        for (int i = 0; i < nbr; ++i) {
+            HIP_TRY(hipEventRecord(b->br_events[i + 1], b->br_streams[i]), "hipEventRecord(join)");
+            HIP_TRY(hipStreamWaitEvent(b->cap_stream, b->br_events[i + 1], 0), "hipStreamWaitEvent");
+        }
+        return CORR_OK;
+    };
+    const int rc = enqueue();
+    const hipError_t ec = hipStreamEndCapture(b->cap_stream, &b->graph);
+    if (rc) return rc;
+    HIP_TRY(ec, "hipStreamEndCapture");
+    HIP_TRY(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+    return CORR_OK;
+}
+
+// Persistent mode: plan every job as one chunk, lay out the work list and
+// capture the graph.
 int batch_build(corr_ctx *b) {
     HIP_TRY(hipSetDevice(b->device), "hipSetDevice");
     const int nj = (int)b->jobs.size();
@@ -893,6 +978,7 @@ corr_ctx *batch_job(corr_handle b, int job) {
 }
 
 int batch_check_error(corr_ctx *b) {
+    if (!b->bctr) return CORR_OK;  // branches mode: no dependency waits
     unsigned err = 0;
     HIP_TRY(hipMemcpy(&err, b->bctr + 1, sizeof err, hipMemcpyDeviceToHost), "hipMemcpy(batch error)");
     if (err) return fail(CORR_EHIP, "batch: a dependency wait exceeded its limit; results are invalid");
@@ -911,8 +997,12 @@ int corr_batch_process(corr_handle b, const void *const *packed, void *stream) {
             return fail(CORR_ESTATE, "job %d (INT8): read the previous integration first", j);
     }
     if (!b->gexec) {
-        int rc = batch_build(b);
-        if (rc) return rc;
+        if (b->bfailed) return fail(CORR_ESTATE, "this batch failed to build; destroy it");
+        int rc = b->bmode == CORR_BATCH_PERSISTENT ? batch_build(b) : batch_build_branches(b);
+        if (rc) {
+            b->bfailed = true;
+            return rc;
+        }
     }
     hipStream_t st = (hipStream_t)stream;
     // pageable source: the copy is staged before this call returns

@@ -3,10 +3,12 @@
 For one job shape (N antennas, K channels, n_spectra, precision) it times
 every candidate (chunk_spectra, x_splits, f_group) with the library's own
 stage timers (HIP events on the launch stream) over a few integrations of
-synthetic input, and keeps the fastest.  Batch jobs (one chunk per job, the
-F-stage group fixed by the batch kernel) are tuned over x_splits in a batch of
-their own.  Results go to a JSON table keyed by (arch, N, K, n_spectra,
-precision[, batch]) that Correlator(tiles="auto") and Batch(tiles="auto") read.
+synthetic input, and keeps the fastest.  Jobs of the persistent batch kernel
+(one chunk per job, the F-stage group fixed by that kernel) are tuned over
+x_splits in a persistent batch of their own.  Results go to a JSON table keyed
+by (arch, N, K, n_spectra, precision[, batch]) that Correlator(tiles="auto")
+and Batch(tiles="auto") read; a branches-mode batch runs the single-job
+kernels and reads the single-job entries.
 
 Run on the GPU:  python -m paper_1102_0148_amd.tune --out tuned.json [shapes]
 """
@@ -124,7 +126,7 @@ def tune_batch_job(N: int, K: int, S: int, prec: str, log=print) -> Tuple[dict, 
     for s in SPLITS:
         if prec != "int8" and S / s > MAX_SPECTRA_PER_PARTIAL:
             continue
-        b = corr.Batch([(N, K, S, prec)], tiles={0: {"x_splits": s}})
+        b = corr.Batch([(N, K, S, prec)], tiles={0: {"x_splits": s}}, mode="persistent")
         try:
             b.process([x])
             b.read_cps_raw(0)

@@ -1,5 +1,6 @@
-"""GPU parity of the batched path (one persistent kernel replayed from a HIP
-graph) against the CPU oracle and against the single-job path."""
+"""GPU parity of the batched path, in both of its modes (each job's own
+kernels on parallel branches of one HIP graph; one persistent kernel replayed
+from a HIP graph), against the CPU oracle and against the single-job path."""
 import numpy as np
 import pytest
 import torch
@@ -10,6 +11,7 @@ import synth
 from test_gpu_parity import coef_error, raw_to_complex
 
 pytestmark = pytest.mark.gpu
+MODES = ["branches", "persistent"]
 
 # uneven jobs: every channel count, 1-6 antenna blocks, both precisions
 JOBS = [(8, 128, 40, "int8"), (12, 256, 64, "fp32"), (16, 512, 33, "int8"), (24, 256, 50, "fp32"),
@@ -37,10 +39,11 @@ def _check_job(raw, N, K, S, prec, packed):
     assert coef_error(raw_to_complex(raw), ref, N) <= tol
 
 
-def test_batch_matches_oracle_and_single_job():
-    print(f"\n[batch] {len(JOBS)} jobs", flush=True)
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_matches_oracle_and_single_job(mode):
+    print(f"\n[batch {mode}] {len(JOBS)} jobs", flush=True)
     inputs = _inputs(JOBS)
-    b = corr.Batch(JOBS)
+    b = corr.Batch(JOBS, mode=mode)
     b.process(inputs)
     raws = [b.read_cps_raw(j) for j in range(len(JOBS))]
     for j, (N, K, S, prec) in enumerate(JOBS):
@@ -60,13 +63,16 @@ def test_batch_matches_oracle_and_single_job():
             assert coef_error(raw_to_complex(single), ref, N) <= (1e-5 if prec == "fp32" else 2e-3)
 
 
-def test_batch_graph_replays():
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_graph_replays(mode):
     """Replay the captured graph several times with eager work and
     synchronisations between replays.  Every replay, the first included, is
     checked: int8 jobs bit-exactly against the single-job path, float jobs
     against the oracle, and every replay equals the first.  (The last job's
     counters are the last of the counter array, and its dumps are the last
-    items; a wrong counter index there once showed only in the first run.)"""
+    items; a wrong counter index there once showed only in the first run.)
+    From the third replay on the inputs are copies at other addresses: the
+    graph reads each job's input pointer at run time."""
     jobs = JOBS[:6]
     inputs = _inputs(jobs, seed0=200)
     singles = {}
@@ -76,10 +82,13 @@ def test_batch_graph_replays():
             c.process(inputs[j])
             singles[j] = c.read_cps_raw()
             c.close()
-    b = corr.Batch(jobs)
+    b = corr.Batch(jobs, mode=mode)
     first = None
+    moved = [x.clone() for x in inputs]
     for rep in range(4):
-        b.process(inputs)
+        b.process(inputs if rep < 2 else moved)
+        if rep == 2:
+            del inputs  # the first copies are freed; their memory may be reused
         # eager work of the program between replays
         scratch = torch.randn(1 << 20, device="cuda")
         scratch.mul_(2.0).sum().item()
@@ -90,7 +99,7 @@ def test_batch_graph_replays():
             if prec == "int8":
                 np.testing.assert_array_equal(raws[j], singles[j], err_msg=f"replay {rep} job {j}")
             elif rep == 0:
-                _check_job(raws[j], N, K, S, prec, inputs[j])
+                _check_job(raws[j], N, K, S, prec, moved[j])
         if first is None:
             first = raws
         else:
@@ -101,6 +110,9 @@ def test_batch_graph_replays():
 def test_batch_rejects_bad_input():
     with pytest.raises(corr.CorrError):
         corr.Batch([(1, 256, 10, "fp32")])
+    with pytest.raises(corr.CorrError) as e:
+        corr.Batch([(8, 256, 16, "fp32")], mode=7)
+    assert e.value.code == corr.CORR_EINVAL
     with pytest.raises(corr.CorrError):
         corr.Batch([(8, 256, 70000, "int8")])
     b = corr.Batch([(8, 256, 16, "int8")])
@@ -112,3 +124,6 @@ def test_batch_rejects_bad_input():
     b.read_cps_raw(0)
     with pytest.raises(corr.CorrError):
         corr.corr_batch_set_tiles(b.h, 0, x_splits=4)
+    with pytest.raises(corr.CorrError) as e:
+        corr.corr_batch_set_mode(b.h, corr.CORR_BATCH_PERSISTENT)
+    assert e.value.code == corr.CORR_ESTATE
