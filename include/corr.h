@@ -100,6 +100,23 @@ int corr_get_tiles(corr_handle h, corr_tiles *t);
  * recomputed from this call's calibration window first.  */
 int corr_process(corr_handle h, const void *packed_samples, void *stream);
 
+/* Delay and phase tracking (Section 2.1: where the signal path disperses, a
+ * phase has to be applied to each subband before accumulation in time).
+ * Before the spectra are accumulated, channel k of antenna a's spectrum s
+ * (s counted from 0 in every integration) is multiplied by exp(2 pi i rho),
+ *     rho = k (delay[a] + delay_rate[a] s) / (2K) + phase[a] + phase_rate[a] s
+ * with delays in samples, delay rates in samples per spectrum, phases in
+ * turns and phase rates in turns per spectrum.  A delay of d samples undoes a
+ * delay of the antenna's signal by d samples (a circular shift of each
+ * 2K-sample block by d is undone exactly), so baseline (a, b) is turned by
+ * rho_a - rho_b.  Arguments: HOST arrays of N doubles each, copied before
+ * return; NULL stands for zeros, and four NULLs switch tracking off.  Applies
+ * to the corr_process calls after it (the copy to the device is ordered on
+ * their stream), not to corr_process_spectra.  INT8 scales are unaffected
+ * (a rotation keeps |X|).  CORR_EINVAL for a non-finite value.  */
+int corr_set_tracking(corr_handle h, const double *delay, const double *delay_rate, const double *phase,
+                      const double *phase_rate);
+
 /* Read the integration buffer and clear it.  Waits for `the last stream`
  * used with this handle.  out: HOST pointer to nb*K*2 floats, nb =
  * N(N+1)/2, layout [baseline][channel][re, im], in the units of the

@@ -55,6 +55,7 @@ def _load():
         "orc_quantise": (i32, [P, i32, i32, i32, P, P]),
         "orc_cmac_i64": (i32, [P, i32, i32, i32, i32, P]),
         "orc_vis_single": (i32, [P, i32, i32, i32, i32, i32, i32, P]),
+        "orc_track": (i32, [P, i32, i32, i32, i32, P, P, P, P]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -175,6 +176,20 @@ def vis_single(packed: np.ndarray, S: int, N: int, K: int, a: int, b: int, k: in
     out = np.empty(2, dtype=np.float64)
     _check(_load().orc_vis_single(_ptr(packed), S, N, K, a, b, k, _ptr(out)), "orc_vis_single")
     return complex(out[0], out[1])
+
+
+def track(spec: np.ndarray, delay=None, delay_rate=None, phase=None, phase_rate=None, s0: int = 0) -> np.ndarray:
+    """Spectra [S][N][K] rotated by the per-antenna delay / phase model (a new
+    array); spectrum s is spectrum s0 + s of the integration."""
+    S, N, K = spec.shape
+    pairs = _spec_pairs(spec)
+    arrs = [None if v is None else np.ascontiguousarray(v, dtype=np.float64).ravel()
+            for v in (delay, delay_rate, phase, phase_rate)]
+    for v in arrs:
+        assert v is None or v.size == N
+    ptrs = [None if v is None else _ptr(v) for v in arrs]
+    _check(_load().orc_track(_ptr(pairs), S, N, K, s0, *ptrs), "orc_track")
+    return pairs[..., 0] + 1j * pairs[..., 1]
 
 
 def correlate(packed: np.ndarray, S: int, N: int, K: int) -> np.ndarray:

@@ -19,6 +19,8 @@
  *   cmac      V[a,b,k] = sum_s X[s,a,k] conj(X[s,b,k]),  0 <= a <= b < N
  *   int8 form scales from the calibration window, q = clamp(rint(x*sc)),
  *             then the same cmac in int64 (exact)
+ *   track     X[s,a,k] *= exp(2 pi i rho(s,a,k)), the per-antenna delay and
+ *             phase model applied before accumulation (Section 2.1)
  *
  * Readings of points the paper leaves open (each one a stated choice):
  *   - samples are two's-complement nibbles, -8..7; the low nibble of a byte
@@ -37,7 +39,9 @@
  * Parity status: every function here is pinned by the CPU test suite
  * (brute-force DFT, numpy's FFT, Parseval, Hermitian symmetry, exact integer
  * bins, tone bin, expected correlation coefficient, delay phase slope,
- * identical-input baselines, int64 == float64 on integer input).  The int8
+ * identical-input baselines, int64 == float64 on integer input; tracking:
+ * the DFT shift theorem, quarter and half turns, common-phase invariance and
+ * the removal of a delayed source's phase slope).  The int8
  * calibration rule itself is a reading, not something the paper fixes, so
  * its constants are "parity unpinned" against the paper; the tests pin that
  * the code implements the rule as stated.
@@ -151,6 +155,38 @@ int orc_spectra(const uint8_t *packed, int S, int N, int K, double *out)
         free(re); free(im); free(x);
     }
     return err;
+}
+
+/* Delay and phase tracking (Section 2.1: where the signal path disperses, a
+ * phase is applied to each subband before accumulation in time).  In place on
+ * spec [S][N][K][2], spectrum s being spectrum s0 + s of the integration:
+ *   X[s,a,k] *= exp(2 pi i rho),
+ *   rho = k (delay[a] + delay_rate[a] t) / 2K + phase[a] + phase_rate[a] t,
+ *   t = s0 + s,
+ * with delays in samples and phases in turns.  Each array holds N values, or
+ * is NULL for zeros.  The whole turns of rho are dropped before the cosine
+ * and sine (which changes nothing but the rounding of large arguments).  */
+int orc_track(double *spec, int S, int N, int K, int s0, const double *delay, const double *delay_rate,
+              const double *phase, const double *phase_rate)
+{
+    if (!spec || S < 0 || N < 1 || K < 1) return ORC_EINVAL;
+    for (int64_t s = 0; s < S; ++s) {
+        const double t = (double)(s0 + s);
+        for (int a = 0; a < N; ++a) {
+            const double d = (delay ? delay[a] : 0.0) + (delay_rate ? delay_rate[a] : 0.0) * t;
+            const double p = (phase ? phase[a] : 0.0) + (phase_rate ? phase_rate[a] : 0.0) * t;
+            for (int k = 0; k < K; ++k) {
+                double rho = (double)k * d / (2.0 * K) + p;
+                rho -= floor(rho);
+                const double c = cos(2.0 * ORC_PI * rho), sn = sin(2.0 * ORC_PI * rho);
+                double *x = spec + ((s * N + a) * (int64_t)K + k) * 2;
+                const double re = x[0], im = x[1];
+                x[0] = re * c - im * sn;
+                x[1] = re * sn + im * c;
+            }
+        }
+    }
+    return ORC_OK;
 }
 
 /* X-stage in float64: V[a,b,k] = sum_s X[s,a,k] * conj(X[s,b,k]).

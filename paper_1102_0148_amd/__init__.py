@@ -31,6 +31,7 @@ BATCH_MODES = {"branches": CORR_BATCH_BRANCHES, "persistent": CORR_BATCH_PERSIST
 # Every symbol include/corr.h declares.
 EXPORTS = (
     "corr_create", "corr_set_precision", "corr_set_tiles", "corr_get_tiles", "corr_process",
+    "corr_set_tracking",
     "corr_read_cps", "corr_read_cps_raw", "corr_read_cps_async", "corr_read_scales",
     "corr_spectra_bytes", "corr_process_spectra", "corr_debug_read_spectra", "corr_get_stats",
     "corr_enable_timing", "corr_destroy", "corr_last_error", "corr_batch_create",
@@ -82,6 +83,7 @@ def load(path: str = LIB_PATH):
         "corr_set_tiles": (I, [P, ctypes.POINTER(corr_tiles)]),
         "corr_get_tiles": (I, [P, ctypes.POINTER(corr_tiles)]),
         "corr_process": (I, [P, P, P]),
+        "corr_set_tracking": (I, [P, P, P, P, P]),
         "corr_read_cps": (I, [P, P]),
         "corr_read_cps_raw": (I, [P, P]),
         "corr_read_cps_async": (I, [P, P, P]),
@@ -133,6 +135,21 @@ def corr_create(N: int, K: int, n_spectra: int):
 
 def corr_set_precision(h, mode: int):
     return _check(load().corr_set_precision(h, mode))
+
+
+def corr_set_tracking(h, delay=None, delay_rate=None, phase=None, phase_rate=None, N=None):
+    """Arrays of N float64 (or None for zeros); all None switches tracking off."""
+    arrs = []
+    for v in (delay, delay_rate, phase, phase_rate):
+        if v is None:
+            arrs.append(None)
+        else:
+            a = np.ascontiguousarray(v, dtype=np.float64).ravel()
+            if N is not None and a.size != N:
+                raise ValueError(f"tracking arrays hold N={N} values, got {a.size}")
+            arrs.append(a)
+    ptrs = [None if a is None else _np_ptr(a) for a in arrs]
+    return _check(load().corr_set_tracking(h, *ptrs))
 
 
 def corr_set_tiles(h, chunk_spectra=0, x_splits=0, f_group=0):
@@ -285,6 +302,13 @@ class Correlator:
         """packed: uint8 CUDA tensor holding n_spectra*N*K bytes."""
         assert packed.is_cuda and packed.numel() == self.S * self.N * self.K
         corr_process(self.h, packed.data_ptr(), _stream(stream))
+
+    def set_tracking(self, delay=None, delay_rate=None, phase=None, phase_rate=None):
+        """Per-antenna delay (samples), delay rate (samples per spectrum), phase
+        (turns) and phase rate (turns per spectrum) applied to the spectra
+        before accumulation, from the next process() on; no arguments switch
+        tracking off."""
+        corr_set_tracking(self.h, delay, delay_rate, phase, phase_rate, N=self.N)
 
     def spectra_bytes(self, n_spectra: int) -> int:
         return corr_spectra_bytes(self.h, n_spectra)

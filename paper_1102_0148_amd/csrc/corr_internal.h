@@ -51,6 +51,8 @@ struct FArgs {
     const float2 *tw;         // W_M^j (j < M), W_2M^q (q < M/2), then M zero bytes
     unsigned long long *sat;  // int8 saturation counter
     unsigned *ticket;         // records mode: 8 tile-chunk counters, zero at launch
+    const double4 *track;     // tracking model per antenna (a_pad entries), or null
+    int s_base;               // integration index of the chunk's first spectrum
     int N, a_pad, S;          // S = spectra in this chunk
     int ntq;                  // power mode: time tiles in the window
     int ngroups;              // antenna groups of GA covering [0, N)
@@ -65,7 +67,8 @@ constexpr size_t kTicketBytes = 8 * kTicketStride * sizeof(unsigned);
 
 // Launch the F-stage for complex length M = K (channels).  mode: 0 = spectra
 // records in precision `prec`, over as many persistent workgroups as stay
-// resident (`grid` ignored; a.ticket zeroed first, on the same stream);
+// resident (`grid` ignored; a.ticket zeroed first, on the same stream; with
+// a.track set, the records are rotated by the tracking model);
 // 1 = power sums over the calibration window (records not written), `grid`
 // blocks.  Returns hipSuccess or the error.
 hipError_t launch_fstage(int M, int prec, int ga, int power_mode, const FArgs &a, int grid,

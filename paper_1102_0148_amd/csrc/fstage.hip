@@ -4,6 +4,20 @@
 namespace corr {
 namespace {
 
+// Persistent workgroups; workgroup b runs on XCD b % 8 (round-robin
+// dispatch), and the tiles of XCD x are the range [x t8, (x+1) t8), dealt one
+// by one by that XCD's ticket counter: tiles in flight on one XCD are
+// neighbours (consecutive antenna groups of nearby time records) whose
+// partial lines meet in one L2.
+template <int M, int PREC, int GA, bool TRACK>
+__device__ __forceinline__ void f_records(const FArgs &args, float2 *zbuf, uint32_t *bbuf) {
+    __shared__ int s_tk[2];
+    const int t8 = (args.ntiles + 7) / 8;
+    const int x = blockIdx.x % 8;
+    const int lo = x * t8, hi = min(lo + t8, args.ntiles);
+    f_tiles_dyn<M, PREC, GA, TRACK>(args, lo, hi, args.ticket + kTicketStride * x, s_tk, zbuf, bbuf);
+}
+
 template <int M, int PREC, int GA, bool POWER>
 __global__ __launch_bounds__(kThreads) void fstage_kernel(FArgs kargs) {
     using Sh = FShape<M, PREC, GA, POWER>;
@@ -19,19 +33,20 @@ __global__ __launch_bounds__(kThreads) void fstage_kernel(FArgs kargs) {
     __shared__ float2 zbuf[Sh::NF * Sh::SLOT];
     __shared__ __attribute__((aligned(16))) uint32_t bbuf[Sh::FPR * (M / 4)];
     if constexpr (!POWER) {
-        // persistent workgroups; workgroup b runs on XCD b % 8 (round-robin
-        // dispatch), and the tiles of XCD x are the range [x t8, (x+1) t8),
-        // dealt one by one by that XCD's ticket counter: tiles in flight on
-        // one XCD are neighbours (consecutive antenna groups of nearby time
-        // records) whose partial lines meet in one L2
-        __shared__ int s_tk[2];
-        const int t8 = (args.ntiles + 7) / 8;
-        const int x = blockIdx.x % 8;
-        const int lo = x * t8, hi = min(lo + t8, args.ntiles);
-        f_tiles_dyn<M, PREC, GA>(args, lo, hi, args.ticket + kTicketStride * x, s_tk, zbuf, bbuf);
+        f_records<M, PREC, GA, false>(args, zbuf, bbuf);
     } else {
         f_power_block<M>(args, blockIdx.x, zbuf, bbuf);
     }
+}
+
+// Records with delay and phase tracking: a kernel of its own, so the kernels
+// without tracking are exactly the ones above.
+template <int M, int PREC, int GA>
+__global__ __launch_bounds__(kThreads) void fstage_track_kernel(FArgs args) {
+    using Sh = FShape<M, PREC, GA, false>;
+    __shared__ float2 zbuf[Sh::NF * Sh::SLOT];
+    __shared__ __attribute__((aligned(16))) uint32_t bbuf[Sh::FPR * (M / 4)];
+    f_records<M, PREC, GA, true>(args, zbuf, bbuf);
 }
 
 template <int M, int PREC, int GA, bool POWER>
@@ -39,12 +54,15 @@ hipError_t launch_one(const FArgs &a, int grid, hipStream_t st) {
     if constexpr (FShape<M, PREC, GA, POWER>::LDS > 160 * 1024) {
         return hipErrorInvalidValue;
     } else {
+        const bool track = !POWER && a.track;
         if (!POWER) {
             // as many workgroups (a multiple of 8) as stay resident, at most one
             // per tile
             int per_cu = 0, dev = 0, cus = 0;
-            hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, fstage_kernel<M, PREC, GA, POWER>, kThreads, 0);
+            hipError_t e = track ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                       &per_cu, fstage_track_kernel<M, PREC, GA>, kThreads, 0)
+                                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                       &per_cu, fstage_kernel<M, PREC, GA, POWER>, kThreads, 0);
             if (e == hipSuccess) e = hipGetDevice(&dev);
             if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
             if (e != hipSuccess) return e;
@@ -56,7 +74,10 @@ hipError_t launch_one(const FArgs &a, int grid, hipStream_t st) {
             const hipError_t z = launch_fill_zero(a.ticket, kTicketBytes, st);
             if (z != hipSuccess) return z;
         }
-        hipLaunchKernelGGL((fstage_kernel<M, PREC, GA, POWER>), dim3(grid), dim3(kThreads), 0, st, a);
+        if (track)
+            hipLaunchKernelGGL((fstage_track_kernel<M, PREC, GA>), dim3(grid), dim3(kThreads), 0, st, a);
+        else
+            hipLaunchKernelGGL((fstage_kernel<M, PREC, GA, POWER>), dim3(grid), dim3(kThreads), 0, st, a);
         return hipGetLastError();
     }
 }

@@ -381,14 +381,51 @@ __device__ __forceinline__ void tile_scales(const FArgs &args, int g, float *slo
     }
 }
 
+// Delay and phase tracking (Section 2.1: a phase applied to each subband
+// before accumulation in time): channel ch of spectra s0 .. s0 + TS - 1 of
+// one antenna, with model m = (delay, delay rate, phase, phase rate), is
+// multiplied by exp(2 pi i rho), rho = ch (m.x + m.y s) / 2M + m.z + m.w s
+// turns.  The phase of spectrum s0 and the step from one spectrum to the
+// next are formed in double and reduced to [-1/2, 1/2] turns, so long
+// integrations and large delays lose nothing to the argument's size; the
+// hardware sine and cosine take turns; the record's later spectra follow by
+// complex multiplication by the step (at most 7 steps).
+template <int M, int TS>
+__device__ __forceinline__ void track_rotate(const double4 &m, int ch, int s0, float *re, float *im) {
+    const double kf = (double)ch * (1.0 / (2.0 * M));
+    const double nu = fma(kf, m.y, m.w);
+    const double rb = fma((double)s0, nu, fma(kf, m.x, m.z));
+    const float fb = (float)(rb - rint(rb));
+    float c = __builtin_amdgcn_cosf(fb), sn = __builtin_amdgcn_sinf(fb);
+    float cs = 1.0f, ss = 0.0f;
+    if constexpr (TS > 1) {
+        const float fs = (float)(nu - rint(nu));
+        cs = __builtin_amdgcn_cosf(fs);
+        ss = __builtin_amdgcn_sinf(fs);
+    }
+#pragma unroll
+    for (int ts = 0; ts < TS; ++ts) {
+        const float x = re[ts], y = im[ts];
+        re[ts] = x * c - y * sn;
+        im[ts] = x * sn + y * c;
+        if (ts + 1 < TS) {
+            const float c2 = c * cs - sn * ss;
+            sn = c * ss + sn * cs;
+            c = c2;
+        }
+    }
+}
+
 // One tile (time record tq, antenna group g) of records from frames already
-// loaded: TS spectra of GA antennas transformed, turned into bins and written
-// as records.  The caller separates consecutive tiles with a barrier.
-template <int M, int PREC, int GA>
+// loaded: TS spectra of GA antennas transformed, turned into bins, rotated by
+// the tracking model trk of the thread's antenna (TRACK) and written as
+// records.  The caller separates consecutive tiles with a barrier.
+template <int M, int PREC, int GA, bool TRACK = false>
 __device__ __forceinline__ void tile_records(const FArgs &args, int tq, int g,
                                              const u32x4 (&cur)[FShape<M, PREC, GA, false>::ROUNDS],
                                              const TileConsts<M, PREC, GA> &k, const float *slo, const float *shi,
-                                             unsigned &wsat, float2 *zbuf, uint32_t *bbuf) {
+                                             unsigned &wsat, float2 *zbuf, uint32_t *bbuf,
+                                             const double4 &trk = double4{0, 0, 0, 0}) {
     using Sh = FShape<M, PREC, GA, false>;
     constexpr int TS = Sh::TS, SLOT = Sh::SLOT, NTASK = Sh::NTASK, TPT = Sh::TPT;
     const int tid = threadIdx.x;
@@ -408,6 +445,11 @@ __device__ __forceinline__ void tile_records(const FArgs &args, int tq, int g,
             lr[ts] = xlo.x; li[ts] = xlo.y; hr[ts] = xhi.x; hi[ts] = xhi.y;
         }
         const int clo = q, chi = q == 0 ? M / 2 : M - q;
+        if constexpr (TRACK) {
+            const int s0 = args.s_base + tq * TS;
+            track_rotate<M, TS>(trk, clo, s0, lr, li);
+            track_rotate<M, TS>(trk, chi, s0, hr, hi);
+        }
         const uint4 rlo = make_record<PREC, TS>(lr, li, slo[it], wsat);
         const uint4 rhi = make_record<PREC, TS>(hr, hi, shi[it], wsat);
         args.spec[rec_index(clo, tq, a, M, args.a_pad)] = rlo;
@@ -460,7 +502,7 @@ __device__ __forceinline__ void f_tiles(const FArgs &args, int t0, int stride, i
 // so all finish together.  Thread 0 takes the ticket of the tile after next
 // when a tile starts and publishes it in s_tk before the barrier that ends the
 // tile, so the atomic's latency hides behind a tile.
-template <int M, int PREC, int GA>
+template <int M, int PREC, int GA, bool TRACK = false>
 __device__ __forceinline__ void f_tiles_dyn(const FArgs &args, int lo, int hi, unsigned *ctr, int *s_tk,
                                             float2 *zbuf, uint32_t *bbuf) {
     using Sh = FShape<M, PREC, GA, false>;
@@ -487,13 +529,18 @@ __device__ __forceinline__ void f_tiles_dyn(const FArgs &args, int lo, int hi, u
         const int tq = tile / args.ngroups, g = tile % args.ngroups;
         float slo[TPT], shi[TPT];
         tile_scales<M, PREC, GA>(args, g, slo, shi);
+        // the thread's antenna is the same for all its tasks (kThreads is a
+        // multiple of GA); loaded, like the scales, before the prefetch, so
+        // waiting for it does not wait for the next tile's frames
+        double4 trk{0, 0, 0, 0};
+        if constexpr (TRACK) trk = args.track[g * GA + tid % GA];
         u32x4 cur[ROUNDS];
 #pragma unroll
         for (int r = 0; r < ROUNDS; ++r) cur[r] = raw[r];
         // the last tile re-reads its own frames rather than branch around the load
         const int pf = next < hi ? next : tile;
         load_tile<M, GA, TS, NF, ROUNDS>(args, pf / args.ngroups, pf % args.ngroups, raw);
-        tile_records<M, PREC, GA>(args, tq, g, cur, k, slo, shi, wsat, zbuf, bbuf);
+        tile_records<M, PREC, GA, TRACK>(args, tq, g, cur, k, slo, shi, wsat, zbuf, bbuf, trk);
         if (tid == 0) s_tk[0] = (int)tk;
         __syncthreads();  // zbuf and bbuf are rewritten by the next tile; s_tk published
         if (next >= hi) break;

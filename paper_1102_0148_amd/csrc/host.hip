@@ -127,6 +127,12 @@ struct corr_ctx {
     // a job of a branches-mode batch: its input pointer, which the kernels
     // read from this device slot when the graph replays
     const uint8_t *const *in_slot = nullptr;
+    // delay and phase tracking: the model per antenna (a_pad entries of
+    // delay, delay rate, phase, phase rate) on the host, copied to the device
+    // table on the next processing stream when changed
+    std::vector<double4> track_host;
+    double4 *track = nullptr;
+    bool track_on = false, track_dirty = false;
     // state
     int64_t accumulated = 0;
     int last_chunk = 0;
@@ -179,8 +185,9 @@ void free_ctx(corr_ctx *h) {
     if (h->cap_stream) hipStreamDestroy(h->cap_stream);
     for (hipStream_t s : h->br_streams) hipStreamDestroy(s);
     for (hipEvent_t e : h->br_events) hipEventDestroy(e);
-    void *bufs[] = {h->spec,   h->partial, h->acc,   h->stage,   h->tw,   h->scales, h->power,
-                    h->regions, h->sat, h->fticket, h->xgroups, h->bjobs, h->in_ptrs, h->items, h->bctr};
+    void *bufs[] = {h->spec,    h->partial, h->acc,     h->stage,   h->tw,     h->scales,
+                    h->power,   h->regions, h->sat,     h->fticket, h->xgroups, h->bjobs,
+                    h->in_ptrs, h->items,   h->bctr,    h->track};
     for (void *p : bufs)
         if (p) hipFree(p);
     for (corr_ctx *j : h->jobs) free_ctx(j);
@@ -360,12 +367,21 @@ int process_one(corr_ctx *h, const uint8_t *in, hipStream_t st) {
     const int ngroups = (h->N + ga - 1) / ga;
     const int64_t frame = (int64_t)h->N * h->K;
     if (h->in_slot && chunk < h->S) return fail(CORR_EINVAL, "a job read through an input slot is one chunk");
+    if (h->track_on && h->track_dirty) {
+        // pageable source: the copy is staged before this call returns
+        HIP_TRY(hipMemcpyAsync(h->track, h->track_host.data(), h->track_host.size() * sizeof(double4),
+                               hipMemcpyHostToDevice, st),
+                "hipMemcpyAsync(tracking)");
+        h->track_dirty = false;
+    }
     for (int c0 = 0; c0 < h->S; c0 += chunk) {
         const int Sc = std::min(chunk, h->S - c0);
         const int ntq_used = round_up((Sc + h->TG - 1) / h->TG, 4);
         FArgs fa{};
         fa.in = h->in_slot ? nullptr : in + (int64_t)c0 * frame;
         fa.in_slot = h->in_slot;
+        fa.track = h->track_on ? h->track : nullptr;
+        fa.s_base = c0;
         fa.spec = h->spec;
         fa.scales = h->scales;
         fa.tw = h->tw;
@@ -590,6 +606,35 @@ int corr_process(corr_handle hh, const void *packed, void *stream) {
     rc = process_one(h, (const uint8_t *)packed, st);
     if (rc) return rc;
     h->accumulated += h->S;
+    return CORR_OK;
+}
+
+int corr_set_tracking(corr_handle hh, const double *delay, const double *delay_rate, const double *phase,
+                      const double *phase_rate) {
+    corr_ctx *h = single(hh);
+    if (!h) return fail(CORR_EINVAL, "invalid handle");
+    const double *src[4] = {delay, delay_rate, phase, phase_rate};
+    if (!delay && !delay_rate && !phase && !phase_rate) {
+        h->track_on = false;
+        return CORR_OK;
+    }
+    for (int m = 0; m < 4; ++m)
+        for (int a = 0; src[m] && a < h->N; ++a)
+            if (!std::isfinite(src[m][a])) return fail(CORR_EINVAL, "tracking value %d of antenna %d is not finite", m, a);
+    if (!h->track) {
+        HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+        HIP_TRY(hipMalloc(&h->track, (size_t)h->a_pad * sizeof(double4)), "hipMalloc(tracking)");
+    }
+    h->track_host.assign(h->a_pad, double4{0, 0, 0, 0});
+    for (int a = 0; a < h->N; ++a) {
+        double4 &t = h->track_host[a];
+        t.x = delay ? delay[a] : 0.0;
+        t.y = delay_rate ? delay_rate[a] : 0.0;
+        t.z = phase ? phase[a] : 0.0;
+        t.w = phase_rate ? phase_rate[a] : 0.0;
+    }
+    h->track_on = true;
+    h->track_dirty = true;
     return CORR_OK;
 }
 

@@ -312,3 +312,77 @@ def test_oracle_rejects_bad_arguments(orc):
         orc.fft(np.zeros(12, dtype=np.complex128))
     with pytest.raises(ValueError):
         orc.spectra(np.zeros(2 * 3 * 100, dtype=np.uint8), 2, 3, 100)
+
+
+# ------------------------------------------------------------------ tracking
+
+def _shifted_blocks(rng, S, N, two_k, shifts):
+    """Random 4-bit blocks x[s][a][n] and the same blocks circularly delayed:
+    y[s][a][n] = x[s][a][(n - shifts[s][a]) mod 2K]."""
+    x = rng.integers(-8, 8, size=(S, N, two_k)).astype(np.int8)
+    y = np.empty_like(x)
+    for s in range(S):
+        for a in range(N):
+            y[s, a] = np.roll(x[s, a], int(shifts[s][a]))
+    return x, y
+
+
+def test_track_undoes_circular_delays(orc):
+    """DFT shift theorem: delaying a block circularly by d samples multiplies
+    bin k by exp(-2 pi i k d / 2K), so a tracking delay of d restores the
+    undelayed spectrum exactly (up to float64 rounding).  The delay rate is
+    pinned the same way, with the shift growing by whole samples per spectrum
+    from a start other than spectrum 0 of the integration."""
+    rng = np.random.default_rng(5)
+    S, N, two_k = 6, 5, 64
+    K = two_k // 2
+    d0 = np.array([0, 3, -7, 12, 30], dtype=np.float64)
+    rate = np.array([0, 1, -2, 0, 5], dtype=np.float64)
+    s0 = 4
+    shifts = [[d0[a] + rate[a] * (s0 + s) for a in range(N)] for s in range(S)]
+    x, y = _shifted_blocks(rng, S, N, two_k, shifts)
+    ref = orc.spectra(synth.pack(torch.from_numpy(x)).numpy(), S, N, K)
+    got = orc.track(orc.spectra(synth.pack(torch.from_numpy(y)).numpy(), S, N, K),
+                    delay=d0, delay_rate=rate, s0=s0)
+    assert np.max(np.abs(got - ref)) < 1e-9 * max(1.0, np.max(np.abs(ref)))
+    # without the correction the spectra do differ
+    assert np.max(np.abs(orc.spectra(synth.pack(torch.from_numpy(y)).numpy(), S, N, K) - ref)) > 1.0
+
+
+def test_track_quarter_and_half_turns(orc):
+    """phase 1/4 turn multiplies by i; a phase rate of 1/2 turn per spectrum
+    alternates the sign; whole turns change nothing."""
+    rng = np.random.default_rng(6)
+    S, N, K = 4, 3, 16
+    spec = rng.standard_normal((S, N, K)) + 1j * rng.standard_normal((S, N, K))
+    got = orc.track(spec, phase=np.full(N, 0.25))
+    np.testing.assert_allclose(got, 1j * spec, rtol=0, atol=1e-12)
+    got = orc.track(spec, phase_rate=np.full(N, 0.5))
+    sign = np.array([(-1.0) ** s for s in range(S)])[:, None, None]
+    np.testing.assert_allclose(got, sign * spec, rtol=0, atol=1e-12)
+    got = orc.track(spec, phase=np.array([1.0, -3.0, 7.0]), delay=np.array([0.0, 2 * K, -4 * K]))
+    np.testing.assert_allclose(got, spec, rtol=0, atol=1e-11)
+
+
+def test_track_common_model_leaves_visibilities(orc):
+    """The same phase and phase rate on every antenna cancel in X_a conj(X_b)."""
+    rng = np.random.default_rng(7)
+    S, N, K = 5, 4, 8
+    spec = rng.standard_normal((S, N, K)) + 1j * rng.standard_normal((S, N, K))
+    got = orc.cmac_f64(orc.track(spec, phase=np.full(N, 0.37), phase_rate=np.full(N, 0.011)))
+    np.testing.assert_allclose(got, orc.cmac_f64(spec), rtol=1e-12, atol=1e-9)
+
+
+def test_track_removes_delay_phase_slope(orc):
+    """The delayed common source of test_delay_phase_slope (d_a = a samples):
+    tracking with delay a on antenna a flattens every baseline's phase."""
+    S, N, two_k = 512, 4, 256
+    K = two_k // 2
+    r = synth.Recipe(N=N, two_k=two_k, seed=4, sources=[synth.Source(rho=0.5, delay_per_antenna=1.0)])
+    spec = orc.track(orc.spectra(synth.packed(r, 0, S).numpy(), S, N, K), delay=np.arange(N, dtype=np.float64))
+    vis = orc.cmac_f64(spec)
+    k = np.arange(1, K)
+    for a in range(N):
+        for b in range(a + 1, N):
+            phase = np.unwrap(np.angle(vis[orc.baseline_index(N, a, b), 1:]))
+            assert abs(np.polyfit(k, phase, 1)[0] * two_k / (2 * math.pi)) < 0.05
