@@ -100,6 +100,55 @@ int corr_get_tiles(corr_handle h, corr_tiles *t);
  * recomputed from this call's calibration window first.  */
 int corr_process(corr_handle h, const void *packed_samples, void *stream);
 
+/* Frames (Section 2.2: each packet is one FFT block of every element and is
+ * self-contained, its header carrying the sample timing, the datatype and
+ * the number of elements; packets are striped over several links, so they can
+ * be lost, repeated or out of order).  A frame is a 32-byte header followed
+ * by the block's N*K payload bytes in the corr_process layout ([antenna][K
+ * bytes]).  All fields little-endian.  */
+#define CORR_FRAME_MAGIC 0x4D52464Fu /* bytes "OFRM" */
+#define CORR_FRAME_VERSION 1
+#define CORR_DTYPE_INT4 1 /* two's-complement nibbles, low nibble first */
+#define CORR_FRAME_HEADER_BYTES 32
+typedef struct {
+    uint32_t magic;      /* CORR_FRAME_MAGIC */
+    uint16_t version;    /* CORR_FRAME_VERSION */
+    uint16_t datatype;   /* CORR_DTYPE_INT4 */
+    uint64_t seq;        /* block number: time of the first sample / 2K samples */
+    uint32_t n_elements; /* N */
+    uint32_t n_samples;  /* 2K samples per element */
+    uint64_t reserved;   /* 0 */
+} corr_frame_header;
+
+typedef struct {
+    int64_t frames_accepted;  /* valid headers inside the integration's range */
+    int64_t frames_rejected;  /* bad magic, version, datatype, N or 2K, or seq out of range */
+    int64_t frames_duplicate; /* accepted but not used: a lower-index frame had the same seq */
+    int64_t spectra_lost;     /* spectra no frame arrived for (zero-filled) */
+} corr_ingest_stats;
+
+/* Assemble one integration of n_spectra spectra from frames.  frames: DEVICE
+ * buffer, 16-byte aligned, frame i at frames + i * frame_stride (stride a
+ * multiple of 16, at least 32 + N*K).  out: DEVICE buffer of n_spectra*N*K
+ * bytes, 16-byte aligned, written in the corr_process layout.  Frame i is
+ * accepted when its header has the magic, version and datatype above,
+ * n_elements == N, n_samples == 2K and first_seq <= seq < first_seq +
+ * n_spectra; it fills spectrum seq - first_seq.  Of several accepted frames
+ * for one spectrum the lowest i is used, so the result does not depend on
+ * scheduling.  A spectrum with no accepted frame is zero-filled, and adds
+ * nothing to the correlation.  Enqueued on `stream`; the counts are read
+ * with corr_get_ingest_stats.  The handle's next corr_process treats this
+ * integration's lost spectra as lost: its INT8 calibration divides by the
+ * spectra received in the window, not by the window's length (enqueue it on
+ * the same stream, or order the two streams).  n_frames may be 0
+ * (everything lost).  CORR_EINVAL for bad pointers, alignment, stride or
+ * count.  */
+int corr_ingest(corr_handle h, const void *frames, int64_t n_frames, int64_t frame_stride, uint64_t first_seq,
+                void *out, void *stream);
+/* Counts of the last corr_ingest; waits for its stream.  CORR_ESTATE if
+ * there was none.  */
+int corr_get_ingest_stats(corr_handle h, corr_ingest_stats *out);
+
 /* Delay and phase tracking (Section 2.1: where the signal path disperses, a
  * phase has to be applied to each subband before accumulation in time).
  * Before the spectra are accumulated, channel k of antenna a's spectrum s

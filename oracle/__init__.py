@@ -56,6 +56,8 @@ def _load():
         "orc_cmac_i64": (i32, [P, i32, i32, i32, i32, P]),
         "orc_vis_single": (i32, [P, i32, i32, i32, i32, i32, i32, P]),
         "orc_track": (i32, [P, i32, i32, i32, i32, P, P, P, P]),
+        "orc_ingest": (i32, [P, i64, i64, ctypes.c_uint64, i32, i32, i32, i32, P, P, P]),
+        "orc_scales_n": (i32, [P, i32, i32, i32, i32, i32, P]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -176,6 +178,30 @@ def vis_single(packed: np.ndarray, S: int, N: int, K: int, a: int, b: int, k: in
     out = np.empty(2, dtype=np.float64)
     _check(_load().orc_vis_single(_ptr(packed), S, N, K, a, b, k, _ptr(out)), "orc_vis_single")
     return complex(out[0], out[1])
+
+
+def ingest(frames: np.ndarray, n_frames: int, stride: int, first_seq: int, S: int, N: int, K: int,
+           W: int = 1024):
+    """Frames (uint8, n_frames x stride) -> (packed uint8 [S][N][K], stats
+    dict, blocks received in the first min(S, W))."""
+    frames = np.ascontiguousarray(frames, dtype=np.uint8)
+    out = np.empty((S, N, K), dtype=np.uint8)
+    st = np.zeros(4, dtype=np.int64)
+    wv = np.zeros(1, dtype=np.int64)
+    _check(_load().orc_ingest(_ptr(frames), n_frames, stride, first_seq, S, N, K, min(S, W), _ptr(out),
+                              _ptr(st), _ptr(wv)), "orc_ingest")
+    stats = dict(frames_accepted=int(st[0]), frames_rejected=int(st[1]), frames_duplicate=int(st[2]),
+                 spectra_lost=int(st[3]))
+    return out, stats, int(wv[0])
+
+
+def scales_n(spec: np.ndarray, W: int, n_div: int) -> np.ndarray:
+    """int8 scales over the first W spectra with the mean taken over n_div."""
+    S, N, K = spec.shape
+    pairs = _spec_pairs(spec)
+    out = np.empty((N, K), dtype=np.float32)
+    _check(_load().orc_scales_n(_ptr(pairs), S, N, K, W, n_div, _ptr(out)), "orc_scales_n")
+    return out
 
 
 def track(spec: np.ndarray, delay=None, delay_rate=None, phase=None, phase_rate=None, s0: int = 0) -> np.ndarray:

@@ -189,6 +189,76 @@ int orc_track(double *spec, int S, int N, int K, int s0, const double *delay, co
     return ORC_OK;
 }
 
+/* Frame ingest (Section 2.2: packets are self-contained FFT blocks of every
+ * element whose headers give sample timing, datatype and element count, and
+ * they may be lost, repeated or reordered in transit).  A frame is a 32-byte
+ * little-endian header -- magic 0x4D52464F, version (16 bits) 1, datatype
+ * (16 bits) 1 = 4-bit, block number (64 bits), elements (32 bits), samples
+ * per element (32 bits), 8 reserved bytes -- then N*K payload bytes.  Frames
+ * are taken in index order; a frame is used when its header is valid for
+ * this (N, 2K), its block lies in [first_seq, first_seq + S), and no earlier
+ * frame filled that block.  Blocks no frame fills are zero.  stats: accepted,
+ * rejected, duplicate frames, lost blocks; window_valid: blocks received
+ * among the first W.  */
+static uint64_t le_get(const uint8_t *p, int nbytes)
+{
+    uint64_t v = 0;
+    for (int i = nbytes - 1; i >= 0; --i) v = (v << 8) | p[i];
+    return v;
+}
+
+int orc_ingest(const uint8_t *frames, int64_t n_frames, int64_t stride, uint64_t first_seq, int S, int N, int K,
+               int W, uint8_t *out, int64_t *stats, int64_t *window_valid)
+{
+    if ((!frames && n_frames > 0) || !out || !stats || !window_valid || S < 0 || N < 1 || K < 1) return ORC_EINVAL;
+    const int64_t payload = (int64_t)N * K;
+    if (stride < 32 + payload) return ORC_EINVAL;
+    uint8_t *filled = (uint8_t *)calloc(S > 0 ? S : 1, 1);
+    if (!filled) return ORC_ENOMEM;
+    memset(out, 0, (size_t)S * payload);
+    stats[0] = stats[1] = stats[2] = stats[3] = 0;
+    for (int64_t i = 0; i < n_frames; ++i) {
+        const uint8_t *f = frames + i * stride;
+        const uint64_t seq = le_get(f + 8, 8);
+        const int ok = le_get(f, 4) == 0x4D52464Fu && le_get(f + 4, 2) == 1 && le_get(f + 6, 2) == 1 &&
+                       le_get(f + 16, 4) == (uint64_t)N && le_get(f + 20, 4) == (uint64_t)(2 * K) &&
+                       seq >= first_seq && seq - first_seq < (uint64_t)S;
+        if (!ok) { stats[1]++; continue; }
+        stats[0]++;
+        const int64_t slot = (int64_t)(seq - first_seq);
+        if (filled[slot]) { stats[2]++; continue; }
+        filled[slot] = 1;
+        memcpy(out + slot * payload, f + 32, (size_t)payload);
+    }
+    *window_valid = 0;
+    for (int s = 0; s < S; ++s) {
+        if (!filled[s]) stats[3]++;
+        else if (s < W) (*window_valid)++;
+    }
+    free(filled);
+    return ORC_OK;
+}
+
+/* int8 scales whose mean power divides by n_div spectra (the ones received
+ * in the window) instead of W; lost spectra are zero and add no power.  */
+int orc_scales_n(const double *spec, int S, int N, int K, int W, int n_div, float *scales)
+{
+    if (!spec || !scales || N < 1 || K < 1 || W < 1 || W > S || n_div < 0) return ORC_EINVAL;
+    for (int a = 0; a < N; ++a) {
+        for (int k = 0; k < K; ++k) {
+            double p = 0.0;
+            for (int s = 0; s < W; ++s) {
+                const double *x = spec + (((int64_t)s * N + a) * K + k) * 2;
+                p += x[0] * x[0] + x[1] * x[1];
+            }
+            double sc = 1.0;
+            if (p > 0.0 && n_div > 0) sc = 127.0 / (4.0 * sqrt(p / (2.0 * n_div)));
+            scales[(int64_t)a * K + k] = (float)sc;
+        }
+    }
+    return ORC_OK;
+}
+
 /* X-stage in float64: V[a,b,k] = sum_s X[s,a,k] * conj(X[s,b,k]).
  * spec: [S][N][K][2].  full == 0: vis is [nb][K][2] over a <= b (baseline
  * order above); full != 0: vis is [N][N][K][2] over every ordered pair.

@@ -31,7 +31,7 @@ BATCH_MODES = {"branches": CORR_BATCH_BRANCHES, "persistent": CORR_BATCH_PERSIST
 # Every symbol include/corr.h declares.
 EXPORTS = (
     "corr_create", "corr_set_precision", "corr_set_tiles", "corr_get_tiles", "corr_process",
-    "corr_set_tracking",
+    "corr_set_tracking", "corr_ingest", "corr_get_ingest_stats",
     "corr_read_cps", "corr_read_cps_raw", "corr_read_cps_async", "corr_read_scales",
     "corr_spectra_bytes", "corr_process_spectra", "corr_debug_read_spectra", "corr_get_stats",
     "corr_enable_timing", "corr_destroy", "corr_last_error", "corr_batch_create",
@@ -59,6 +59,11 @@ class corr_stats(ctypes.Structure):
                 ("launches_f", ctypes.c_int64), ("launches_x", ctypes.c_int64)]
 
 
+class corr_ingest_stats(ctypes.Structure):
+    _fields_ = [("frames_accepted", ctypes.c_int64), ("frames_rejected", ctypes.c_int64),
+                ("frames_duplicate", ctypes.c_int64), ("spectra_lost", ctypes.c_int64)]
+
+
 class corr_job(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int), ("K", ctypes.c_int), ("n_spectra", ctypes.c_int),
                 ("precision", ctypes.c_int)]
@@ -84,6 +89,8 @@ def load(path: str = LIB_PATH):
         "corr_get_tiles": (I, [P, ctypes.POINTER(corr_tiles)]),
         "corr_process": (I, [P, P, P]),
         "corr_set_tracking": (I, [P, P, P, P, P]),
+        "corr_ingest": (I, [P, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64, P, P]),
+        "corr_get_ingest_stats": (I, [P, ctypes.POINTER(corr_ingest_stats)]),
         "corr_read_cps": (I, [P, P]),
         "corr_read_cps_raw": (I, [P, P]),
         "corr_read_cps_async": (I, [P, P, P]),
@@ -135,6 +142,17 @@ def corr_create(N: int, K: int, n_spectra: int):
 
 def corr_set_precision(h, mode: int):
     return _check(load().corr_set_precision(h, mode))
+
+
+def corr_ingest(h, frames_ptr: int, n_frames: int, frame_stride: int, first_seq: int, out_ptr: int,
+                stream: int = 0):
+    return _check(load().corr_ingest(h, frames_ptr, n_frames, frame_stride, first_seq, out_ptr, stream))
+
+
+def corr_get_ingest_stats(h) -> dict:
+    st = corr_ingest_stats()
+    _check(load().corr_get_ingest_stats(h, ctypes.byref(st)))
+    return {name: getattr(st, name) for name, _ in corr_ingest_stats._fields_}
 
 
 def corr_set_tracking(h, delay=None, delay_rate=None, phase=None, phase_rate=None, N=None):
@@ -302,6 +320,21 @@ class Correlator:
         """packed: uint8 CUDA tensor holding n_spectra*N*K bytes."""
         assert packed.is_cuda and packed.numel() == self.S * self.N * self.K
         corr_process(self.h, packed.data_ptr(), _stream(stream))
+
+    def ingest(self, frames, n_frames: int, frame_stride: int, first_seq: int, out=None, stream=None):
+        """Assemble this integration from frames (a uint8 CUDA tensor holding
+        n_frames frames of frame_stride bytes) into `out` (a uint8 CUDA tensor
+        of n_spectra*N*K bytes, allocated if None), which is returned."""
+        assert frames.is_cuda and frames.numel() >= n_frames * frame_stride
+        if out is None:
+            import torch
+            out = torch.empty(self.S * self.N * self.K, dtype=torch.uint8, device=frames.device)
+        assert out.is_cuda and out.numel() == self.S * self.N * self.K
+        corr_ingest(self.h, frames.data_ptr(), n_frames, frame_stride, first_seq, out.data_ptr(), _stream(stream))
+        return out
+
+    def ingest_stats(self) -> dict:
+        return corr_get_ingest_stats(self.h)
 
     def set_tracking(self, delay=None, delay_rate=None, phase=None, phase_rate=None):
         """Per-antenna delay (samples), delay rate (samples per spectrum), phase

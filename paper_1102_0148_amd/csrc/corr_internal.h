@@ -114,12 +114,25 @@ hipError_t launch_xgroups(int prec, const XArgs &a, hipStream_t st);
 // acc[f][bl] (double2) += sum over splits of partial[sp][f][bl], in split order.
 hipError_t launch_dump(int prec, const void *partial, double2 *acc, int nsplit, int K, int nb,
                        hipStream_t st);
-// scales[a][f] from power partials summed in order over nparts.
+// scales[a][f] from power partials summed in order over nparts; the mean
+// power divides by W spectra, or by *w_valid when given (the spectra of the
+// window that arrived, counted on the device by the frame ingest).
 hipError_t launch_scales(const float *power, int nparts, int N, int a_pad, int K, int W,
-                         float *scales, hipStream_t st);
+                         const unsigned *w_valid, float *scales, hipStream_t st);
 // dst[bl][f] = acc[f][bl] (raw layout), then acc = 0.
 hipError_t launch_finalize(double2 *acc, double2 *dst, int K, int nb, hipStream_t st);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st);
+
+// ---------------------------------------------------------------- ingest
+// Counters of one ingest: accepted frames, rejected frames, lost spectra,
+// spectra received in the calibration window.
+constexpr size_t kIngestCounterBytes = 4 * sizeof(unsigned);
+// Assemble S spectra of N x K bytes into `out` from n_frames frames (header
+// and payload as in corr.h) at `stride` bytes: `owner` (S entries rounded up
+// to a multiple of 4) and `counters` are scratch, cleared here; W is the
+// calibration window.
+hipError_t launch_ingest(const uint8_t *frames, int64_t n_frames, int64_t stride, uint64_t first_seq, int S,
+                         int N, int K, int W, unsigned *owner, unsigned *counters, uint8_t *out, hipStream_t st);
 
 // ---------------------------------------------------------------- batch
 // One correlation job of a batch, as the persistent kernel sees it.  F-stage

@@ -13,9 +13,10 @@ __global__ __launch_bounds__(256) void dump_kernel(const P *partial, double2 *ac
 }
 
 __global__ __launch_bounds__(256) void scales_kernel(const float *power, int nparts, int N, int a_pad,
-                                                     int K, int W, float *scales) {
+                                                     int K, int W, const unsigned *w_valid, float *scales) {
     const int e = blockIdx.x * 256 + threadIdx.x;
-    if (e < N * K) scales[e] = scale_one(power, nparts, a_pad, K, W, e);
+    const int w = w_valid ? (int)*w_valid : W;
+    if (e < N * K) scales[e] = scale_one(power, nparts, a_pad, K, w, e);
 }
 
 // dst[bl][f] = acc[f][bl]; acc = 0
@@ -48,9 +49,10 @@ hipError_t launch_dump(int prec, const void *partial, double2 *acc, int nsplit, 
 }
 
 hipError_t launch_scales(const float *power, int nparts, int N, int a_pad, int K, int W,
-                         float *scales, hipStream_t st) {
+                         const unsigned *w_valid, float *scales, hipStream_t st) {
     const int grid = (N * K + 255) / 256;
-    hipLaunchKernelGGL(scales_kernel, dim3(grid), dim3(256), 0, st, power, nparts, N, a_pad, K, W, scales);
+    hipLaunchKernelGGL(scales_kernel, dim3(grid), dim3(256), 0, st, power, nparts, N, a_pad, K, W, w_valid,
+                       scales);
     return hipGetLastError();
 }
 

@@ -27,7 +27,7 @@ __device__ __forceinline__ float scale_one(const float *power, int nparts, int a
     float p = 0.0f;
     for (int i = 0; i < nparts; ++i) p += power[((int64_t)i * a_pad + ant) * K + c];
     float sc = 1.0f;
-    if (p > 0.0f) {
+    if (p > 0.0f && W > 0) {
         const float rms = sqrtf(p / (2.0f * (float)W));
         sc = 127.0f / (4.0f * rms);
     }

@@ -133,6 +133,13 @@ struct corr_ctx {
     std::vector<double4> track_host;
     double4 *track = nullptr;
     bool track_on = false, track_dirty = false;
+    // frame ingest: owner table and counters of the last corr_ingest, and
+    // whether the next corr_process still has to take its lost spectra into
+    // account
+    unsigned *ingest_owner = nullptr;
+    unsigned *ingest_ctr = nullptr;
+    hipStream_t ingest_stream = nullptr;
+    bool ingested = false, ingest_pending = false;
     // state
     int64_t accumulated = 0;
     int last_chunk = 0;
@@ -187,7 +194,7 @@ void free_ctx(corr_ctx *h) {
     for (hipEvent_t e : h->br_events) hipEventDestroy(e);
     void *bufs[] = {h->spec,    h->partial, h->acc,     h->stage,   h->tw,     h->scales,
                     h->power,   h->regions, h->sat,     h->fticket, h->xgroups, h->bjobs,
-                    h->in_ptrs, h->items,   h->bctr,    h->track};
+                    h->in_ptrs, h->items,   h->bctr,    h->track,   h->ingest_owner, h->ingest_ctr};
     for (void *p : bufs)
         if (p) hipFree(p);
     for (corr_ctx *j : h->jobs) free_ctx(j);
@@ -350,7 +357,9 @@ int calibrate(corr_ctx *h, const uint8_t *in, hipStream_t st) {
     fa.ntiles = fa.ntq;
     timer_begin(h, 0, st);
     HIP_TRY(launch_fstage(h->K, kFP32, gp, 1, fa, fa.ngroups * nparts, st), "calibration launch");
-    HIP_TRY(launch_scales(h->power, nparts, h->N, h->a_pad, h->K, W, h->scales, st), "scales launch");
+    // after a frame ingest, the spectra of the window that arrived
+    const unsigned *w_valid = h->ingest_pending ? h->ingest_ctr + 3 : nullptr;
+    HIP_TRY(launch_scales(h->power, nparts, h->N, h->a_pad, h->K, W, w_valid, h->scales, st), "scales launch");
     timer_end(h, st);
     return CORR_OK;
 }
@@ -605,7 +614,50 @@ int corr_process(corr_handle hh, const void *packed, void *stream) {
     h->last_stream = st;
     rc = process_one(h, (const uint8_t *)packed, st);
     if (rc) return rc;
+    h->ingest_pending = false;
     h->accumulated += h->S;
+    return CORR_OK;
+}
+
+int corr_ingest(corr_handle hh, const void *frames, int64_t n_frames, int64_t frame_stride, uint64_t first_seq,
+                void *out, void *stream) {
+    corr_ctx *h = single(hh);
+    if (!h) return fail(CORR_EINVAL, "invalid handle");
+    if (n_frames < 0 || n_frames > 0x7fffffff) return fail(CORR_EINVAL, "n_frames=%lld out of [0, 2^31)", (long long)n_frames);
+    if (n_frames > 0 && (!frames || (reinterpret_cast<uintptr_t>(frames) & 15)))
+        return fail(CORR_EINVAL, "frames must be a 16-byte aligned device pointer");
+    const int64_t payload = (int64_t)h->N * h->K;
+    if (frame_stride % 16 || frame_stride < CORR_FRAME_HEADER_BYTES + payload)
+        return fail(CORR_EINVAL, "frame_stride=%lld must be a multiple of 16 and at least %lld", (long long)frame_stride,
+                    (long long)(CORR_FRAME_HEADER_BYTES + payload));
+    if (!out || (reinterpret_cast<uintptr_t>(out) & 15)) return fail(CORR_EINVAL, "out must be a 16-byte aligned device pointer");
+    HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+    if (!h->ingest_owner) {
+        HIP_TRY(hipMalloc(&h->ingest_owner, (size_t)(h->S + 3) / 4 * 16), "hipMalloc(ingest owners)");
+        HIP_TRY(hipMalloc(&h->ingest_ctr, kIngestCounterBytes), "hipMalloc(ingest counters)");
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const int W = std::min(h->S, CORR_CALIB_SPECTRA);
+    HIP_TRY(launch_ingest((const uint8_t *)frames, n_frames, frame_stride, first_seq, h->S, h->N, h->K, W,
+                          h->ingest_owner, h->ingest_ctr, (uint8_t *)out, st),
+            "ingest launch");
+    h->ingest_stream = st;
+    h->ingested = true;
+    h->ingest_pending = true;
+    return CORR_OK;
+}
+
+int corr_get_ingest_stats(corr_handle hh, corr_ingest_stats *out) {
+    corr_ctx *h = single(hh);
+    if (!h || !out) return fail(CORR_EINVAL, "invalid handle or out");
+    if (!h->ingested) return fail(CORR_ESTATE, "no corr_ingest yet");
+    HIP_TRY(hipStreamSynchronize(h->ingest_stream), "hipStreamSynchronize");
+    unsigned c[4] = {0, 0, 0, 0};
+    HIP_TRY(hipMemcpy(c, h->ingest_ctr, sizeof c, hipMemcpyDeviceToHost), "hipMemcpy(ingest counters)");
+    out->frames_accepted = c[0];
+    out->frames_rejected = c[1];
+    out->spectra_lost = c[2];
+    out->frames_duplicate = (int64_t)c[0] - ((int64_t)h->S - c[2]);
     return CORR_OK;
 }
 

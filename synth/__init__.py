@@ -166,3 +166,44 @@ def batch_jobs(n_jobs: int = 12, seed: int = 3) -> List[Recipe]:
         N, two_k = BATCH_SHAPES[i]
         jobs.append(Recipe(N=N, two_k=two_k, sources=[Source(rho=r)], seed=seed * 1000 + j))
     return jobs
+
+
+# Frames: the packet form of the input (Section 2.2: each packet is one FFT
+# block of every element, with a header giving its sample timing, datatype and
+# element count).  The header layout is the library's interface: 32 bytes,
+# little-endian, magic "OFRM", version 1, datatype 1 (4-bit), block number,
+# elements, samples per element, 8 reserved bytes.
+FRAME_MAGIC = 0x4D52464F
+FRAME_HEADER_BYTES = 32
+
+
+def frames(packed, seqs, blocks=None, stride: Optional[int] = None, two_k: Optional[int] = None,
+           magic: int = FRAME_MAGIC, version: int = 1, datatype: int = 1, n_elements: Optional[int] = None):
+    """Frames carrying packed blocks: packed uint8 [S][N][K]; frame i holds
+    block blocks[i] (default i) and says it is block seqs[i].  Header fields
+    can be given per frame (sequences) or for all frames, so tests can build
+    corrupt headers.  Returns uint8 [n_frames][stride] (CPU)."""
+    import numpy as np
+    p = packed.cpu().numpy() if hasattr(packed, "cpu") else np.asarray(packed)
+    S, N, K = p.shape
+    n = len(seqs)
+    blocks = list(range(n)) if blocks is None else list(blocks)
+    payload = N * K
+    stride = stride or (FRAME_HEADER_BYTES + payload + 15) // 16 * 16
+    out = np.zeros((n, stride), dtype=np.uint8)
+
+    def per(v, i):
+        return v[i] if isinstance(v, (list, tuple, np.ndarray)) else v
+
+    for i in range(n):
+        hdr = np.zeros(FRAME_HEADER_BYTES, dtype=np.uint8)
+        hdr[0:4] = np.frombuffer(np.uint32(per(magic, i)).tobytes(), dtype=np.uint8)
+        hdr[4:6] = np.frombuffer(np.uint16(per(version, i)).tobytes(), dtype=np.uint8)
+        hdr[6:8] = np.frombuffer(np.uint16(per(datatype, i)).tobytes(), dtype=np.uint8)
+        hdr[8:16] = np.frombuffer(np.uint64(seqs[i]).tobytes(), dtype=np.uint8)
+        ne = N if n_elements is None else per(n_elements, i)
+        hdr[16:20] = np.frombuffer(np.uint32(ne).tobytes(), dtype=np.uint8)
+        hdr[20:24] = np.frombuffer(np.uint32(2 * K if two_k is None else per(two_k, i)).tobytes(), dtype=np.uint8)
+        out[i, :FRAME_HEADER_BYTES] = hdr
+        out[i, FRAME_HEADER_BYTES:FRAME_HEADER_BYTES + payload] = p[blocks[i]].reshape(-1)
+    return torch.from_numpy(out)

@@ -386,3 +386,65 @@ def test_track_removes_delay_phase_slope(orc):
         for b in range(a + 1, N):
             phase = np.unwrap(np.angle(vis[orc.baseline_index(N, a, b), 1:]))
             assert abs(np.polyfit(k, phase, 1)[0] * two_k / (2 * math.pi)) < 0.05
+
+
+# ------------------------------------------------------------------- ingest
+
+def _blocks(S, N, K, seed):
+    rng = np.random.default_rng(seed)
+    return torch.from_numpy(rng.integers(0, 256, size=(S, N, K), dtype=np.uint8))
+
+
+def test_ingest_in_order_and_shuffled(orc):
+    """Every block once, in order and shuffled, from a block number that is
+    not 0: the integration is the blocks themselves."""
+    S, N, K, first = 12, 3, 64, 1000
+    p = _blocks(S, N, K, 1)
+    for order in (np.arange(S), np.random.default_rng(2).permutation(S)):
+        fr = synth.frames(p, [first + int(b) for b in order], blocks=list(order))
+        out, st, wv = orc.ingest(fr.numpy(), S, fr.shape[1], first, S, N, K, W=5)
+        np.testing.assert_array_equal(out, p.numpy())
+        assert st == dict(frames_accepted=S, frames_rejected=0, frames_duplicate=0, spectra_lost=0)
+        assert wv == 5
+
+
+def test_ingest_lost_duplicate_and_rejected(orc):
+    """Lost blocks are zero; of two frames for one block the earlier one is
+    used; every kind of bad header is rejected."""
+    S, N, K, first = 10, 4, 64, 7
+    p = _blocks(S, N, K, 3)
+    other = _blocks(S, N, K, 4)
+    seqs = [first + b for b in (5, 0, 2, 5, 9, 1)]          # blocks 3, 4, 6, 7, 8 lost; 5 twice
+    blocks = [5, 0, 2, 5, 9, 1]
+    fr = synth.frames(p, seqs, blocks=blocks)
+    dup = synth.frames(other, [first + 5], blocks=[5])        # a later, different frame for block 5
+    bad = [synth.frames(p, [first + 3], blocks=[3], magic=0x12345678),
+           synth.frames(p, [first + 3], blocks=[3], version=2),
+           synth.frames(p, [first + 3], blocks=[3], datatype=2),
+           synth.frames(p, [first + 3], blocks=[3], n_elements=N + 1),
+           synth.frames(p, [first + 3], blocks=[3], two_k=4 * K),
+           synth.frames(p, [first - 1], blocks=[3]),
+           synth.frames(p, [first + S], blocks=[3])]
+    allf = torch.cat([fr, dup] + bad).numpy()
+    out, st, wv = orc.ingest(allf, allf.shape[0], allf.shape[1], first, S, N, K, W=4)
+    ref = np.zeros_like(p.numpy())
+    for b in (0, 1, 2, 5, 9):
+        ref[b] = p.numpy()[b]
+    np.testing.assert_array_equal(out, ref)
+    assert st == dict(frames_accepted=7, frames_rejected=7, frames_duplicate=2, spectra_lost=5)
+    assert wv == 3                                            # blocks 0, 1, 2 of the first 4
+
+
+def test_scales_over_received_spectra(orc):
+    """Dividing by the received spectra equals the plain rule on the window
+    with the lost spectra left out."""
+    rng = np.random.default_rng(8)
+    S, N, K, W = 20, 3, 16, 12
+    spec = rng.standard_normal((S, N, K)) + 1j * rng.standard_normal((S, N, K))
+    np.testing.assert_array_equal(orc.scales_n(spec, W, W), orc.scales(spec, W))
+    lost = [1, 4, 5, 11]
+    zeroed = spec.copy()
+    zeroed[lost] = 0
+    kept = np.delete(spec[:W], lost, axis=0)
+    np.testing.assert_allclose(orc.scales_n(zeroed, W, W - len(lost)), orc.scales(kept, W - len(lost)),
+                               rtol=1e-6)
