@@ -21,6 +21,9 @@
  *             then the same cmac in int64 (exact)
  *   track     X[s,a,k] *= exp(2 pi i rho(s,a,k)), the per-antenna delay and
  *             phase model applied before accumulation (Section 2.1)
+ *   ingest    frames (header + block) put into their blocks in index order,
+ *             lost blocks zero, and the scales over the received blocks
+ *             (Section 2.2)
  *
  * Readings of points the paper leaves open (each one a stated choice):
  *   - samples are two's-complement nibbles, -8..7; the low nibble of a byte
@@ -41,7 +44,9 @@
  * bins, tone bin, expected correlation coefficient, delay phase slope,
  * identical-input baselines, int64 == float64 on integer input; tracking:
  * the DFT shift theorem, quarter and half turns, common-phase invariance and
- * the removal of a delayed source's phase slope).  The int8
+ * the removal of a delayed source's phase slope; ingest: hand-built order,
+ * loss, repeats and every header fault, and the scales over received blocks
+ * against the plain rule on the window without the lost blocks).  The int8
  * calibration rule itself is a reading, not something the paper fixes, so
  * its constants are "parity unpinned" against the paper; the tests pin that
  * the code implements the rule as stated.
