@@ -71,8 +71,10 @@ def make_inputs(device):
     return bufs
 
 
-def run_form(corr, torch, precision, inputs, steps, warmup, timing=False):
+def run_form(corr, torch, precision, inputs, steps, warmup, timing=False, tracking=None):
     c = corr.Correlator(N_ANT, K, S_INT, precision=precision, tiles="auto")
+    if tracking:
+        c.set_tracking(**tracking)
     dst = torch.empty(c.nb * K * 2, dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
 
@@ -101,6 +103,64 @@ def run_form(corr, torch, precision, inputs, steps, warmup, timing=False):
     tiles = c.tiles()
     c.close()
     return ms / steps, wall / steps * 1e3, stats, tiles
+
+
+def tracking_leg(corr, torch, metrics, inputs, steps, warmup, forms):
+    """The headline step with per-antenna delay and phase tracking switched on
+    (delays up to 50 samples, with rates), in each form, against the same
+    step without it."""
+    import numpy as np
+    rng = np.random.default_rng(1)
+    model = dict(delay=rng.uniform(-50, 50, N_ANT), delay_rate=rng.uniform(-1e-3, 1e-3, N_ANT),
+                 phase=rng.uniform(-1, 1, N_ANT), phase_rate=rng.uniform(-1e-4, 1e-4, N_ANT))
+    a_s = N_INT * metrics.antenna_samples(N_ANT, TWO_K, S_INT)
+    out = {"model": "per-antenna delay U(-50, 50) samples, rate U(-1e-3, 1e-3) samples/spectrum, "
+                    "phase U(-1, 1) turns, rate U(-1e-4, 1e-4) turns/spectrum"}
+    for name in forms:
+        ms, _, stats, _ = run_form(corr, torch, name, inputs, steps, warmup, timing=True, tracking=model)
+        n_int = steps * N_INT
+        out[name] = {"antenna_msps": round(a_s / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4),
+                     "f_ms_per_integration": round(stats["ms_f"] / n_int, 4),
+                     "untracked_f_ms_per_integration": forms[name]["ms_per_integration"]["f"]}
+        log(f"[bench] tracking {name}: {out[name]}")
+    return out
+
+
+def ingest_leg(corr, torch, packed):
+    """One N = 44 integration assembled from its 65536 frames, shuffled, by
+    corr_ingest (frames built on the GPU from one header template)."""
+    import synth
+    S = S_INT
+    stride = (synth.FRAME_HEADER_BYTES + N_ANT * K + 15) // 16 * 16
+    hdr = synth.frames(packed[:1].cpu().view(1, N_ANT, K), [0])[0, :synth.FRAME_HEADER_BYTES].cuda()
+    frames = torch.empty(S, stride, dtype=torch.uint8, device="cuda")
+    frames[:, :synth.FRAME_HEADER_BYTES] = hdr
+    frames[:, 8:16] = torch.arange(S, dtype=torch.int64, device="cuda").view(torch.uint8).view(S, 8)
+    frames[:, synth.FRAME_HEADER_BYTES:synth.FRAME_HEADER_BYTES + N_ANT * K] = packed.view(S, N_ANT * K)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    frames = frames[torch.randperm(S, device="cuda", generator=g)].contiguous()
+    c = corr.Correlator(N_ANT, K, S)
+    out = torch.empty(S * N_ANT * K, dtype=torch.uint8, device="cuda")
+    c.ingest(frames, S, stride, 0, out)
+    torch.cuda.synchronize()
+    exact = bool(torch.equal(out, packed.view(-1)))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        c.ingest(frames, S, stride, 0, out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    st = c.ingest_stats()
+    c.close()
+    nbytes = S * stride + S * N_ANT * K
+    res = {"workload": f"{S} frames of {stride} bytes (N={N_ANT}, {TWO_K}-pt), shuffled",
+           "ms_per_integration": round(ms, 4), "gb_per_s": round(nbytes / (ms * 1e-3) / 1e9, 1),
+           "bytes_moved": nbytes, "assembled_exactly": exact, "stats": st}
+    log(f"[bench] ingest: {res}")
+    return res
 
 
 def accuracy(corr, torch, precision):
@@ -244,7 +304,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-spectra", type=int, default=8192)
+    ap.add_argument("--cpu-spectra", type=int, default=65536)
     ap.add_argument("--forms", default="fp32,fp16,int8")
     ap.add_argument("--no-extra", action="store_true", help="skip the large-N and batch workloads")
     ap.add_argument("--copy-probe", action="store_true",
@@ -347,6 +407,8 @@ def main():
         "roofline": roof,
     }
     if not args.no_extra:
+        out["tracking"] = tracking_leg(corr, torch, metrics, inputs, max(2, args.steps // 3), 1, forms)
+        out["ingest"] = ingest_leg(corr, torch, inputs[0])
         del inputs
         torch.cuda.empty_cache()
         out["large_n"] = large_n(corr, torch, metrics, max(2, args.steps // 3), 1)
