@@ -305,7 +305,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-spectra", type=int, default=65536)
-    ap.add_argument("--forms", default="fp32,fp16,int8")
+    ap.add_argument("--forms", default="fp32,fp16,int8,int16")
     ap.add_argument("--no-extra", action="store_true", help="skip the large-N and batch workloads")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (scale reference for HBM counters)")
@@ -348,8 +348,8 @@ def main():
             "launches_per_integration": {"f": stats["launches_f"] // n_int, "x": stats["launches_x"] // n_int},
             "tiles": tiles,
         }
-        if name == "int8":
-            forms[name]["int8_saturated_fraction"] = stats["int8_saturated"] / max(
+        if name in ("int8", "int16"):
+            forms[name]["saturated_fraction"] = stats["int8_saturated"] / max(
                 1, (args.steps + args.warmup) * N_INT * S_INT * N_ANT * K * 2)
         log(f"[bench] {name}: {forms[name]}")
     for name in forms:

@@ -55,8 +55,12 @@ enum corr_status {
 /* Arithmetic of the X-stage.  FP32: float spectra, float products and sums.
  * FP16: spectra rounded to half (ties to even), float accumulation.  INT8:
  * spectra requantised per antenna and channel (Section 4's conversion to a
- * short integer type with prescaling, here to 8 bits), exact int32 sums.  */
-enum corr_precision { CORR_FP32 = 0, CORR_FP16 = 1, CORR_INT8 = 2 };
+ * short integer type with prescaling, here to 8 bits), exact int32 sums.
+ * INT16: the same requantisation to 16 bits (the paper's short complex type;
+ * codes within +-32512), products summed exactly (int32 digit sums combined
+ * into exact integers); needs x_splits >= chunk_spectra / 16384, which the
+ * default satisfies; not available in batches.  */
+enum corr_precision { CORR_FP32 = 0, CORR_FP16 = 1, CORR_INT8 = 2, CORR_INT16 = 3 };
 
 /* Limits checked by corr_create.  */
 #define CORR_MAX_ANTENNAS 512

@@ -57,7 +57,9 @@ def _load():
         "orc_vis_single": (i32, [P, i32, i32, i32, i32, i32, i32, P]),
         "orc_track": (i32, [P, i32, i32, i32, i32, P, P, P, P]),
         "orc_ingest": (i32, [P, i64, i64, ctypes.c_uint64, i32, i32, i32, i32, P, P, P]),
-        "orc_scales_n": (i32, [P, i32, i32, i32, i32, i32, P]),
+        "orc_scales_n": (i32, [P, i32, i32, i32, i32, i32, ctypes.c_double, P]),
+        "orc_quantise16": (i32, [P, i32, i32, i32, P, P]),
+        "orc_cmac_i64_16": (i32, [P, i32, i32, i32, i32, P]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -195,13 +197,36 @@ def ingest(frames: np.ndarray, n_frames: int, stride: int, first_seq: int, S: in
     return out, stats, int(wv[0])
 
 
-def scales_n(spec: np.ndarray, W: int, n_div: int) -> np.ndarray:
-    """int8 scales over the first W spectra with the mean taken over n_div."""
+def scales_n(spec: np.ndarray, W: int, n_div: int, qmax: float = 127.0) -> np.ndarray:
+    """Scales over the first W spectra with the mean taken over n_div, for the
+    largest code qmax (127: int8, 32512: int16)."""
     S, N, K = spec.shape
     pairs = _spec_pairs(spec)
     out = np.empty((N, K), dtype=np.float32)
-    _check(_load().orc_scales_n(_ptr(pairs), S, N, K, W, n_div, _ptr(out)), "orc_scales_n")
+    _check(_load().orc_scales_n(_ptr(pairs), S, N, K, W, n_div, float(qmax), _ptr(out)), "orc_scales_n")
     return out
+
+
+def quantise16(spec: np.ndarray, sc: np.ndarray) -> np.ndarray:
+    """complex spectra [S][N][K] + scales [N][K] -> int16 [S][N][K][2]."""
+    S, N, K = spec.shape
+    pairs = _spec_pairs(spec)
+    sc = np.ascontiguousarray(sc, dtype=np.float32)
+    assert sc.shape == (N, K)
+    q = np.empty((S, N, K, 2), dtype=np.int16)
+    _check(_load().orc_quantise16(_ptr(pairs), S, N, K, _ptr(sc), _ptr(q)), "orc_quantise16")
+    return q
+
+
+def cmac_i64_16(q: np.ndarray, full: bool = False) -> np.ndarray:
+    """int16 [S][N][K][2] -> exact int64 visibilities [rows][K][2]."""
+    q = np.ascontiguousarray(q, dtype=np.int16)
+    S, N, K, two = q.shape
+    assert two == 2
+    rows = N * N if full else n_baselines(N)
+    vis = np.empty((rows, K, 2), dtype=np.int64)
+    _check(_load().orc_cmac_i64_16(_ptr(q), S, N, K, int(full), _ptr(vis)), "orc_cmac_i64_16")
+    return vis.reshape(N, N, K, 2) if full else vis
 
 
 def track(spec: np.ndarray, delay=None, delay_rate=None, phase=None, phase_rate=None, s0: int = 0) -> np.ndarray:

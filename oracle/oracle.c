@@ -21,6 +21,8 @@
  *             then the same cmac in int64 (exact)
  *   track     X[s,a,k] *= exp(2 pi i rho(s,a,k)), the per-antenna delay and
  *             phase model applied before accumulation (Section 2.1)
+ *   int16     the same requantisation to codes within +-32512 (Section 4's
+ *             16-bit short complex type), and the cmac on them in int64
  *   ingest    frames (header + block) put into their blocks in index order,
  *             lost blocks zero, and the scales over the received blocks
  *             (Section 2.2)
@@ -44,7 +46,9 @@
  * bins, tone bin, expected correlation coefficient, delay phase slope,
  * identical-input baselines, int64 == float64 on integer input; tracking:
  * the DFT shift theorem, quarter and half turns, common-phase invariance and
- * the removal of a delayed source's phase slope; ingest: hand-built order,
+ * the removal of a delayed source's phase slope; int16: ties and clamp,
+ * int64 sums against numpy, scales 256 times the int8 rule's; ingest:
+ * hand-built order,
  * loss, repeats and every header fault, and the scales over received blocks
  * against the plain rule on the window without the lost blocks).  The int8
  * calibration rule itself is a reading, not something the paper fixes, so
@@ -244,11 +248,12 @@ int orc_ingest(const uint8_t *frames, int64_t n_frames, int64_t stride, uint64_t
     return ORC_OK;
 }
 
-/* int8 scales whose mean power divides by n_div spectra (the ones received
- * in the window) instead of W; lost spectra are zero and add no power.  */
-int orc_scales_n(const double *spec, int S, int N, int K, int W, int n_div, float *scales)
+/* Scales for the largest code qmax (127 for int8, 32512 for int16) whose
+ * mean power divides by n_div spectra (the ones received in the window; W
+ * when none is lost); lost spectra are zero and add no power.  */
+int orc_scales_n(const double *spec, int S, int N, int K, int W, int n_div, double qmax, float *scales)
 {
-    if (!spec || !scales || N < 1 || K < 1 || W < 1 || W > S || n_div < 0) return ORC_EINVAL;
+    if (!spec || !scales || N < 1 || K < 1 || W < 1 || W > S || n_div < 0 || !(qmax > 0)) return ORC_EINVAL;
     for (int a = 0; a < N; ++a) {
         for (int k = 0; k < K; ++k) {
             double p = 0.0;
@@ -257,7 +262,7 @@ int orc_scales_n(const double *spec, int S, int N, int K, int W, int n_div, floa
                 p += x[0] * x[0] + x[1] * x[1];
             }
             double sc = 1.0;
-            if (p > 0.0 && n_div > 0) sc = 127.0 / (4.0 * sqrt(p / (2.0 * n_div)));
+            if (p > 0.0 && n_div > 0) sc = qmax / (4.0 * sqrt(p / (2.0 * n_div)));
             scales[(int64_t)a * K + k] = (float)sc;
         }
     }
@@ -341,6 +346,54 @@ int orc_quantise(const double *spec, int S, int N, int K, const float *scales, i
                 q[i] = quantise_one(spec[i], sc);
                 q[i + 1] = quantise_one(spec[i + 1], sc);
             }
+    return ORC_OK;
+}
+
+/* The 16-bit form (Section 4: the conversion of the float spectra to a short
+ * complex integer type with prescaling): q = clamp(rint(float(x) * sc),
+ * -32512, 32512), decided in float as for int8.  q: [S][N][K][2] int16.  */
+int orc_quantise16(const double *spec, int S, int N, int K, const float *scales, int16_t *q)
+{
+    if (!spec || !scales || !q || S < 0 || N < 1 || K < 1) return ORC_EINVAL;
+    for (int64_t s = 0; s < S; ++s)
+        for (int a = 0; a < N; ++a)
+            for (int k = 0; k < K; ++k) {
+                const int64_t i = ((s * N + a) * K + k) * 2;
+                const float sc = scales[(int64_t)a * K + k];
+                for (int c = 0; c < 2; ++c) {
+                    float r = rintf((float)spec[i + c] * sc);
+                    if (r > 32512.0f) r = 32512.0f;
+                    if (r < -32512.0f) r = -32512.0f;
+                    q[i + c] = (int16_t)r;
+                }
+            }
+    return ORC_OK;
+}
+
+/* Exact integer X-stage on 16-bit spectra, as orc_cmac_i64.  */
+int orc_cmac_i64_16(const int16_t *q, int S, int N, int K, int full, int64_t *vis)
+{
+    if (!q || !vis || S < 0 || N < 1 || K < 1) return ORC_EINVAL;
+    const int64_t nb = (int64_t)N * (N + 1) / 2;
+    const int64_t nout = full ? (int64_t)N * N : nb;
+    memset(vis, 0, sizeof(int64_t) * nout * K * 2);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int a = 0; a < N; ++a) {
+        for (int s = 0; s < S; ++s) {
+            const int16_t *xa = q + ((int64_t)s * N + a) * K * 2;
+            for (int b = full ? 0 : a; b < N; ++b) {
+                const int16_t *xb = q + ((int64_t)s * N + b) * K * 2;
+                int64_t row = full ? (int64_t)a * N + b : orc_baseline_index(N, a, b);
+                int64_t *v = vis + row * K * 2;
+                for (int k = 0; k < K; ++k) {
+                    int64_t ar = xa[2 * k], ai = xa[2 * k + 1];
+                    int64_t br = xb[2 * k], bi = xb[2 * k + 1];
+                    v[2 * k] += ar * br + ai * bi;
+                    v[2 * k + 1] += ai * br - ar * bi;
+                }
+            }
+        }
+    }
     return ORC_OK;
 }
 

@@ -22,9 +22,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcorr.so")
 
 CORR_OK, CORR_EINVAL, CORR_ENOMEM, CORR_EHIP, CORR_ESTATE = 0, -1, -2, -3, -4
-CORR_FP32, CORR_FP16, CORR_INT8 = 0, 1, 2
+CORR_FP32, CORR_FP16, CORR_INT8, CORR_INT16 = 0, 1, 2, 3
 CORR_CALIB_SPECTRA = 1024
-PRECISIONS = {"fp32": CORR_FP32, "fp16": CORR_FP16, "int8": CORR_INT8}
+PRECISIONS = {"fp32": CORR_FP32, "fp16": CORR_FP16, "int8": CORR_INT8, "int16": CORR_INT16}
 CORR_BATCH_BRANCHES, CORR_BATCH_PERSISTENT = 0, 1
 BATCH_MODES = {"branches": CORR_BATCH_BRANCHES, "persistent": CORR_BATCH_PERSISTENT}
 
@@ -387,7 +387,7 @@ class Correlator:
 # ------------------------------------------------ record layout (host side)
 
 def record_times(precision: int) -> int:
-    return {CORR_FP32: 2, CORR_FP16: 4, CORR_INT8: 8}[precision]
+    return {CORR_FP32: 2, CORR_FP16: 4, CORR_INT8: 8, CORR_INT16: 4}[precision]
 
 
 TQB = 16  # records per time block
@@ -398,10 +398,32 @@ def a_pad_of(N: int) -> int:
     return 16 * nblk if nblk <= 6 else (N + 63) // 64 * 64
 
 
+def int16_digits(q: np.ndarray):
+    """Base-255 digits of int16 codes (|q| <= 32512): q = 255 h + l, h and l
+    in [-127, 127]."""
+    q = np.asarray(q, dtype=np.int64)
+    h = (2 * q + 255) // 510          # floor((q + 127.5) / 255)
+    return h.astype(np.int8), (q - 255 * h).astype(np.int8)
+
+
 def spectra_to_records(spec: np.ndarray, precision: int) -> np.ndarray:
-    """Lay out spectra [S][N][K] (complex for fp32/fp16; int8 [S][N][K][2] for
-    int8) as the library's records [tq/16][K][tq%16][a_pad][re x TG | im x TG]."""
+    """Lay out spectra [S][N][K] (complex for fp32/fp16; integer [S][N][K][2]
+    for int8 and int16) as the library's records [tq/16][K][tq%16][a_pad][re x
+    TG | im x TG]; int16 records hold [h of re | h of im | l of re | l of im]
+    (base-255 digits)."""
     tg = record_times(precision)
+    if precision == CORR_INT16:
+        S, N, K, _ = spec.shape
+        a_pad = a_pad_of(N)
+        ntq = ((S + tg - 1) // tg + TQB - 1) // TQB * TQB
+        out = np.zeros((ntq // TQB, K, TQB, a_pad, 2, 2, tg), dtype=np.int8)
+        tq = np.arange(S) // tg
+        tb, tr, tt = tq // TQB, tq % TQB, np.arange(S) % tg
+        for comp in range(2):
+            h, l = int16_digits(np.transpose(spec[..., comp], (0, 2, 1)))
+            out[tb, :, tr, :N, 0, comp, tt] = h
+            out[tb, :, tr, :N, 1, comp, tt] = l
+        return out.view(np.uint8).reshape(-1)
     if precision == CORR_INT8:
         S, N, K, _ = spec.shape
         re, im = spec[..., 0], spec[..., 1]
@@ -422,9 +444,21 @@ def spectra_to_records(spec: np.ndarray, precision: int) -> np.ndarray:
 
 
 def records_to_spectra(buf: np.ndarray, precision: int, N: int, K: int, S: int) -> np.ndarray:
-    """Inverse of spectra_to_records: complex64 [S][N][K] (fp32/fp16, as float)
-    or int8 [S][N][K][2] (int8)."""
+    """Inverse of spectra_to_records: complex64 [S][N][K] (fp32/fp16, as float),
+    int8 [S][N][K][2] (int8) or int16 [S][N][K][2] (int16)."""
     tg = record_times(precision)
+    if precision == CORR_INT16:
+        a_pad = a_pad_of(N)
+        ntq = ((S + tg - 1) // tg + TQB - 1) // TQB * TQB
+        rec = np.asarray(buf).view(np.int8)[: ntq * K * a_pad * 4 * tg].reshape(ntq // TQB, K, TQB, a_pad, 2, 2, tg)
+        tq = np.arange(S) // tg
+        tb, tr, tt = tq // TQB, tq % TQB, np.arange(S) % tg
+        out = []
+        for comp in range(2):
+            h = rec[tb, :, tr, :N, 0, comp, tt].astype(np.int32)
+            l = rec[tb, :, tr, :N, 1, comp, tt].astype(np.int32)
+            out.append(np.transpose(255 * h + l, (0, 2, 1)).astype(np.int16))
+        return np.stack(out, axis=-1)
     dt = {CORR_FP32: np.float32, CORR_FP16: np.float16, CORR_INT8: np.int8}[precision]
     a_pad = a_pad_of(N)
     ntq = ((S + tg - 1) // tg + TQB - 1) // TQB * TQB

@@ -11,13 +11,22 @@ namespace corr {
 constexpr int kFP32 = 0;
 constexpr int kFP16 = 1;
 constexpr int kINT8 = 2;
+constexpr int kINT16 = 3;
+// the requantised forms, which take per-(antenna, channel) scales
+__host__ __device__ constexpr bool is_quant(int prec) { return prec == kINT8 || prec == kINT16; }
+// int16 values: |q| <= 32512 = 255 * 127 + 127, each stored as two int8
+// digits in base 255, q = 255 h + l with h, l in [-127, 127]
+constexpr int kI16Max = 32512;
+// spectra one int16 partial may sum: every digit sum stays below 2^31 (the
+// cross sum adds 4 digit products per spectrum: 4 * 16384 * 127^2 < 2^31)
+constexpr int kI16SplitSpectra = 16384;
 
 // A spectra record is 16 bytes: TG consecutive spectra of one (channel,
 // antenna) as [re x TG][im x TG].  Four records (one per MFMA lane group)
 // form a k-block of the X-stage.
 constexpr int kRecordBytes = 16;
 __host__ __device__ constexpr int record_times(int prec) {
-    return prec == kFP32 ? 2 : (prec == kFP16 ? 4 : 8);
+    return prec == kFP32 ? 2 : (prec == kINT8 ? 8 : 4);
 }
 __host__ __device__ constexpr int kblock_times(int prec) { return 4 * record_times(prec); }
 
@@ -109,6 +118,9 @@ hipError_t launch_xstage(int prec, int rb, int kind, const XArgs &a, hipStream_t
 // int8 / fp16 with 4 x 4-block regions: one workgroup per (group, channel,
 // split), the group's blocks staged through an LDS ring (a.groups).
 hipError_t launch_xgroups(int prec, const XArgs &a, hipStream_t st);
+// int16 (also reached through launch_xstage): rb <= 3 diagonal, rb <= 2 off
+// the diagonal; a.nkb even; partials are double2 (exact integers).
+hipError_t launch_xstage16(int rb, int kind, const XArgs &a, hipStream_t st);
 
 // ---------------------------------------------------------------- dump etc.
 // acc[f][bl] (double2) += sum over splits of partial[sp][f][bl], in split order.
@@ -118,7 +130,7 @@ hipError_t launch_dump(int prec, const void *partial, double2 *acc, int nsplit, 
 // power divides by W spectra, or by *w_valid when given (the spectra of the
 // window that arrived, counted on the device by the frame ingest).
 hipError_t launch_scales(const float *power, int nparts, int N, int a_pad, int K, int W,
-                         const unsigned *w_valid, float *scales, hipStream_t st);
+                         const unsigned *w_valid, float qmax, float *scales, hipStream_t st);
 // dst[bl][f] = acc[f][bl] (raw layout), then acc = 0.
 hipError_t launch_finalize(double2 *acc, double2 *dst, int K, int nb, hipStream_t st);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st);

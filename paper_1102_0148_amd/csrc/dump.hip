@@ -13,10 +13,11 @@ __global__ __launch_bounds__(256) void dump_kernel(const P *partial, double2 *ac
 }
 
 __global__ __launch_bounds__(256) void scales_kernel(const float *power, int nparts, int N, int a_pad,
-                                                     int K, int W, const unsigned *w_valid, float *scales) {
+                                                     int K, int W, const unsigned *w_valid, float qmax,
+                                                     float *scales) {
     const int e = blockIdx.x * 256 + threadIdx.x;
     const int w = w_valid ? (int)*w_valid : W;
-    if (e < N * K) scales[e] = scale_one(power, nparts, a_pad, K, w, e);
+    if (e < N * K) scales[e] = scale_one(power, nparts, a_pad, K, w, e, qmax);
 }
 
 // dst[bl][f] = acc[f][bl]; acc = 0
@@ -42,6 +43,9 @@ hipError_t launch_dump(int prec, const void *partial, double2 *acc, int nsplit, 
     if (prec == kINT8)
         hipLaunchKernelGGL(dump_kernel<int2>, dim3(grid), dim3(256), 0, st,
                            reinterpret_cast<const int2 *>(partial), acc, nsplit, n);
+    else if (prec == kINT16)
+        hipLaunchKernelGGL(dump_kernel<double2>, dim3(grid), dim3(256), 0, st,
+                           reinterpret_cast<const double2 *>(partial), acc, nsplit, n);
     else
         hipLaunchKernelGGL(dump_kernel<float2>, dim3(grid), dim3(256), 0, st,
                            reinterpret_cast<const float2 *>(partial), acc, nsplit, n);
@@ -49,9 +53,9 @@ hipError_t launch_dump(int prec, const void *partial, double2 *acc, int nsplit, 
 }
 
 hipError_t launch_scales(const float *power, int nparts, int N, int a_pad, int K, int W,
-                         const unsigned *w_valid, float *scales, hipStream_t st) {
+                         const unsigned *w_valid, float qmax, float *scales, hipStream_t st) {
     const int grid = (N * K + 255) / 256;
-    hipLaunchKernelGGL(scales_kernel, dim3(grid), dim3(256), 0, st, power, nparts, N, a_pad, K, W, w_valid,
+    hipLaunchKernelGGL(scales_kernel, dim3(grid), dim3(256), 0, st, power, nparts, N, a_pad, K, W, w_valid, qmax,
                        scales);
     return hipGetLastError();
 }

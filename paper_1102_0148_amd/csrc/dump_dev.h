@@ -21,15 +21,17 @@ __device__ __forceinline__ void dump_one(const P *partial, double2 *acc, int nsp
 
 // Scale of (antenna, channel) e = ant * K + c: the power over the window is
 // summed over its nparts partials in order; rms per component is
-// sqrt(P / (2W)); scale = 127 / (4 rms); a channel with no power keeps 1.
-__device__ __forceinline__ float scale_one(const float *power, int nparts, int a_pad, int K, int W, int e) {
+// sqrt(P / (2W)); scale = qmax / (4 rms), qmax being the largest code (127
+// for int8, 32512 for int16); a channel with no power keeps 1.
+__device__ __forceinline__ float scale_one(const float *power, int nparts, int a_pad, int K, int W, int e,
+                                           float qmax = 127.0f) {
     const int ant = e / K, c = e % K;
     float p = 0.0f;
     for (int i = 0; i < nparts; ++i) p += power[((int64_t)i * a_pad + ant) * K + c];
     float sc = 1.0f;
     if (p > 0.0f && W > 0) {
         const float rms = sqrtf(p / (2.0f * (float)W));
-        sc = 127.0f / (4.0f * rms);
+        sc = qmax / (4.0f * rms);
     }
     return sc;
 }

@@ -101,6 +101,7 @@ hipError_t launch_m(int prec, int ga, int power, const FArgs &a, int grid, hipSt
         case kFP32: return launch_mp<M, kFP32>(ga, power, a, grid, st);
         case kFP16: return launch_mp<M, kFP16>(ga, power, a, grid, st);
         case kINT8: return launch_mp<M, kINT8>(ga, power, a, grid, st);
+        case kINT16: return launch_mp<M, kINT16>(ga, power, a, grid, st);
     }
     return hipErrorInvalidValue;
 }

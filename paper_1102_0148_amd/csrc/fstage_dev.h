@@ -204,6 +204,34 @@ __device__ __forceinline__ uint4 make_record(const float *re, const float *im, f
             h[4 + t] = (_Float16)im[t];
         }
         __builtin_memcpy(&out, h, 16);
+    } else if constexpr (PREC == kINT16) {
+        static_assert(TS == 4, "int16 record");
+        // q = clamp(rint(x sc), -32512, 32512) as for int8, then the base-255
+        // digits h = floor((q + 127.5) / 255), l = q - 255 h, both in
+        // [-127, 127] (q + 127.5 is a half-integer, never within 1/510 of a
+        // multiple of 255 after the division, and the product by the
+        // reciprocal is within 2^-16 of the quotient, so the floor is exact).
+        // Record: [h of re x4][h of im x4][l of re x4][l of im x4].
+        uint32_t hb[8], lb[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const float v = (t < 4 ? re[t] : im[t - 4]) * sc;
+            wsat += (unsigned)__popcll(__ballot(fabsf(v) >= (float)kI16Max + 0.5f));
+            const float q = (__builtin_amdgcn_fmed3f(v, -(float)kI16Max, (float)kI16Max) + 12582912.0f) - 12582912.0f;
+            const float h = floorf((q + 127.5f) * (1.0f / 255.0f));
+            const float l = q - 255.0f * h;
+            hb[t] = __float_as_uint(h + 12582912.0f);
+            lb[t] = __float_as_uint(l + 12582912.0f);
+        }
+        uint32_t w[4];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const uint32_t *b = hb + 4 * k;
+            w[k] = __builtin_amdgcn_perm(b[1], b[0], 0x0c0c0400u) | __builtin_amdgcn_perm(b[3], b[2], 0x04000c0cu);
+            const uint32_t *c = lb + 4 * k;
+            w[2 + k] = __builtin_amdgcn_perm(c[1], c[0], 0x0c0c0400u) | __builtin_amdgcn_perm(c[3], c[2], 0x04000c0cu);
+        }
+        out = make_uint4(w[0], w[1], w[2], w[3]);
     } else {
         static_assert(TS == 8, "int8 record");
         // rint and the clamp to +-127 commute, so clamp first; adding 1.5 * 2^23
@@ -370,7 +398,7 @@ __device__ __forceinline__ void tile_scales(const FArgs &args, int g, float *slo
 #pragma unroll
     for (int it = 0; it < Sh::TPT; ++it) {
         slo[it] = shi[it] = 1.0f;
-        if constexpr (PREC == kINT8) {
+        if constexpr (is_quant(PREC)) {
             const int t = threadIdx.x + it * kThreads;
             const bool ok = (Sh::NTASK % kThreads == 0 || t < Sh::NTASK) && g * GA + t % GA < args.N;
             const int a = ok ? g * GA + t % GA : 0, q = ok ? t / GA : 0;
@@ -441,7 +469,7 @@ __device__ __forceinline__ void tile_records(const FArgs &args, int tq, int g,
 #pragma unroll
         for (int ts = 0; ts < TS; ++ts) {
             float2 xlo, xhi;
-            real_bins<M, PREC == kINT8>(zbuf + (ts * GA + ga) * SLOT, q, k.bw[it], xlo, xhi);
+            real_bins<M, is_quant(PREC)>(zbuf + (ts * GA + ga) * SLOT, q, k.bw[it], xlo, xhi);
             lr[ts] = xlo.x; li[ts] = xlo.y; hr[ts] = xhi.x; hi[ts] = xhi.y;
         }
         const int clo = q, chi = q == 0 ? M / 2 : M - q;
@@ -490,7 +518,7 @@ __device__ __forceinline__ void f_tiles(const FArgs &args, int t0, int stride, i
         tile_records<M, PREC, GA>(args, tq, g, cur, k, slo, shi, wsat, zbuf, bbuf);
         __syncthreads();  // zbuf and bbuf are rewritten by the next tile
     }
-    if constexpr (PREC == kINT8) {
+    if constexpr (is_quant(PREC)) {
         if ((threadIdx.x & 63) == 0 && wsat) atomicAdd(args.sat, (unsigned long long)wsat);
     }
 }
@@ -547,7 +575,7 @@ __device__ __forceinline__ void f_tiles_dyn(const FArgs &args, int lo, int hi, u
         tile = next;
         next = lo + s_tk[0];
     }
-    if constexpr (PREC == kINT8) {
+    if constexpr (is_quant(PREC)) {
         if ((threadIdx.x & 63) == 0 && wsat) atomicAdd(args.sat, (unsigned long long)wsat);
     }
 }

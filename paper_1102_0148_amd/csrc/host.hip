@@ -218,13 +218,15 @@ int default_splits(const corr_ctx *h) {
     const int64_t waves_per_split = (int64_t)n_regions(h) * h->K;
     int s = (int)((4096 + waves_per_split - 1) / waves_per_split);
     s = std::max(1, std::min(64, s));
-    // fp32 / fp16 partials cover at most ~2048 spectra each
-    if (h->prec != kINT8) {
-        const int chunk = h->tiles.chunk_spectra;
-        s = std::max(s, std::min(64, (chunk + 2047) / 2048));
-    }
+    // fp32 / fp16 partials cover at most ~2048 spectra each; int16 digit
+    // sums stay exact in int32 over up to 16384
+    const int chunk = h->tiles.chunk_spectra;
+    if (h->prec == kFP32 || h->prec == kFP16) s = std::max(s, std::min(64, (chunk + 2047) / 2048));
+    if (h->prec == kINT16) s = std::max(s, (chunk + kI16SplitSpectra - 1) / kI16SplitSpectra);
     return s;
 }
+
+hipError_t set_regions(corr_ctx *h, int rb);
 
 // Resolve tiles and allocate the precision-dependent scratch.
 int plan(corr_ctx *h) {
@@ -238,12 +240,24 @@ int plan(corr_ctx *h) {
         return fail(CORR_EINVAL, "f_group=%d needs more than 160 KB of LDS at K=%d in this precision",
                     h->tiles.f_group, h->K);
     const int chunk = h->tiles.chunk_spectra;
+    if (h->prec == kINT16) {
+        if ((int64_t)h->tiles.x_splits * kI16SplitSpectra < chunk)
+            return fail(CORR_EINVAL, "INT16 needs x_splits >= %d for chunks of %d spectra (exact int32 digit sums)",
+                        (chunk + kI16SplitSpectra - 1) / kI16SplitSpectra, chunk);
+        // six accumulators per block pair: regions of at most 3 blocks on the
+        // diagonal and 2 off it
+        if (h->rb > 3) {
+            hipError_t e = set_regions(h, h->nblk % 2 == 0 ? 2 : 1);
+            if (e != hipSuccess) return hip_fail(e, "regions");
+        }
+    }
     h->ntq_buf = round_up((chunk + h->TG - 1) / h->TG, kTQB);
     h->spec_bytes = (size_t)h->K * h->ntq_buf * h->a_pad * kRecordBytes;
     HIP_TRY(hipMalloc(&h->spec, h->spec_bytes), "hipMalloc(spectra chunk)");
     HIP_TRY(hipMemset(h->spec, 0, h->spec_bytes), "hipMemset(spectra chunk)");
-    HIP_TRY(hipMalloc(&h->partial, (size_t)h->tiles.x_splits * h->K * h->nb * 8), "hipMalloc(partials)");
-    if (h->prec == kINT8) {
+    HIP_TRY(hipMalloc(&h->partial, (size_t)h->tiles.x_splits * h->K * h->nb * (h->prec == kINT16 ? 16 : 8)),
+            "hipMalloc(partials)");
+    if (is_quant(h->prec)) {
         const int W = std::min(h->S, CORR_CALIB_SPECTRA);
         const int ntq_w = (W + 1) / 2;
         const int nparts = (ntq_w + kCalibTilesPerWG - 1) / kCalibTilesPerWG;
@@ -308,13 +322,14 @@ int launch_x_and_dump(corr_ctx *h, const uint4 *spec, int ntq, int nkb, hipStrea
     timer_begin(h, 2, st);
     xa.regions = h->regions;
     xa.n_diag = h->n_diag;
-    if (h->n_xgroups && h->prec != kFP32) {
+    const bool half_or_byte = h->prec == kFP16 || h->prec == kINT8;
+    if (h->n_xgroups && half_or_byte) {
         // groups of regions that share blocks stage them in LDS once per
         // k-block, with the loads two k-blocks ahead
         xa.groups = h->xgroups;
         xa.ngroups = h->n_xgroups;
         HIP_TRY(launch_xgroups(h->prec, xa, st), "X-stage launch");
-    } else if (h->n_off && h->prec != kFP32) {
+    } else if (h->n_off && half_or_byte) {
         // one launch over every region of a channel (diagonal ones first), so
         // the regions that share records read them from HBM once, through one
         // L2: the int8 and fp16 forms are bound by that traffic
@@ -359,15 +374,17 @@ int calibrate(corr_ctx *h, const uint8_t *in, hipStream_t st) {
     HIP_TRY(launch_fstage(h->K, kFP32, gp, 1, fa, fa.ngroups * nparts, st), "calibration launch");
     // after a frame ingest, the spectra of the window that arrived
     const unsigned *w_valid = h->ingest_pending ? h->ingest_ctr + 3 : nullptr;
-    HIP_TRY(launch_scales(h->power, nparts, h->N, h->a_pad, h->K, W, w_valid, h->scales, st), "scales launch");
+    const float qmax = h->prec == kINT16 ? (float)kI16Max : 127.0f;
+    HIP_TRY(launch_scales(h->power, nparts, h->N, h->a_pad, h->K, W, w_valid, qmax, h->scales, st),
+            "scales launch");
     timer_end(h, st);
     return CORR_OK;
 }
 
 int process_one(corr_ctx *h, const uint8_t *in, hipStream_t st) {
-    if (h->prec == kINT8) {
+    if (is_quant(h->prec)) {
         if (h->accumulated)
-            return fail(CORR_ESTATE, "INT8: read the previous integration before processing the next");
+            return fail(CORR_ESTATE, "INT8/INT16: read the previous integration before processing the next");
         int rc = calibrate(h, in, st);
         if (rc) return rc;
     }
@@ -385,7 +402,8 @@ int process_one(corr_ctx *h, const uint8_t *in, hipStream_t st) {
     }
     for (int c0 = 0; c0 < h->S; c0 += chunk) {
         const int Sc = std::min(chunk, h->S - c0);
-        const int ntq_used = round_up((Sc + h->TG - 1) / h->TG, 4);
+        // whole k-blocks; int16 steps take two k-blocks
+        const int ntq_used = round_up((Sc + h->TG - 1) / h->TG, h->prec == kINT16 ? 8 : 4);
         FArgs fa{};
         fa.in = h->in_slot ? nullptr : in + (int64_t)c0 * frame;
         fa.in_slot = h->in_slot;
@@ -434,7 +452,7 @@ int read_raw_into(corr_ctx *h, double *out) {
 
 int descale_to_float(corr_ctx *h, const double *raw, float *out) {
     const int64_t n = (int64_t)h->nb * h->K;
-    if (h->prec != kINT8) {
+    if (!is_quant(h->prec)) {
         for (int64_t i = 0; i < 2 * n; ++i) out[i] = (float)raw[i];
         return CORR_OK;
     }
@@ -574,7 +592,7 @@ corr_handle corr_create(int N, int K, int n_spectra) {
 int corr_set_precision(corr_handle hh, int mode) {
     corr_ctx *h = single(hh);
     if (!h) return fail(CORR_EINVAL, "invalid handle");
-    if (mode != CORR_FP32 && mode != CORR_FP16 && mode != CORR_INT8)
+    if (mode != CORR_FP32 && mode != CORR_FP16 && mode != CORR_INT8 && mode != CORR_INT16)
         return fail(CORR_EINVAL, "unknown precision %d", mode);
     if (h->started || h->planned) return fail(CORR_ESTATE, "precision is fixed once processing has started");
     if (mode == CORR_INT8 && h->S > 65536)
@@ -721,7 +739,8 @@ int corr_read_cps_async(corr_handle hh, double *dst, void *stream) {
 int corr_read_scales(corr_handle hh, float *out) {
     corr_ctx *h = single(hh);
     if (!h || !out) return fail(CORR_EINVAL, "invalid handle or out");
-    if (h->prec != kINT8 || !h->scales) return fail(CORR_ESTATE, "scales exist only for INT8 after processing");
+    if (!is_quant(h->prec) || !h->scales)
+        return fail(CORR_ESTATE, "scales exist only for INT8 / INT16 after processing");
     HIP_TRY(hipStreamSynchronize(h->last_stream), "hipStreamSynchronize");
     HIP_TRY(hipMemcpy(out, h->scales, (size_t)h->N * h->K * sizeof(float), hipMemcpyDeviceToHost),
             "hipMemcpy(scales)");
@@ -748,7 +767,7 @@ int corr_process_spectra(corr_handle hh, const void *spectra, int n_spectra, voi
     hipStream_t st = (hipStream_t)stream;
     h->started = true;
     h->last_stream = st;
-    const int ntq = round_up((n_spectra + h->TG - 1) / h->TG, 4);
+    const int ntq = round_up((n_spectra + h->TG - 1) / h->TG, h->prec == kINT16 ? 8 : 4);
     rc = launch_x_and_dump(h, (const uint4 *)spectra, ntq, ntq / 4, st);
     if (rc) return rc;
     h->accumulated += n_spectra;
@@ -830,6 +849,11 @@ corr_handle corr_batch_create(const corr_job *jobs, int n_jobs) {
         const corr_job &jd = jobs[i];
         corr_ctx *h = create_ctx(jd.N, jd.K, jd.n_spectra);
         if (h) b->jobs.push_back(h);
+        if (h && jd.precision == CORR_INT16) {
+            free_ctx(b);
+            fail(CORR_EINVAL, "job %d: INT16 is not available in batches", i);
+            return nullptr;
+        }
         if (!h || corr_set_precision(h, jd.precision) != CORR_OK) {
             char msg[512];
             snprintf(msg, sizeof msg, "job %d: %s", i, g_err);

@@ -124,7 +124,45 @@ hipError_t launch_xgroups(int prec, const XArgs &a, hipStream_t st) {
     return hipErrorInvalidValue;
 }
 
+namespace {
+
+// int16: regions of at most 3 blocks on the diagonal and 2 off it (six
+// accumulators per block pair).
+template <int RB, int KIND>
+__global__ __launch_bounds__(256, 2) void xstage16_kernel(XArgs a) {
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lb = (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+    x_wave16<RB, KIND == kDiag>(a, lb * 4 + w);
+}
+
+template <int RB, int KIND>
+hipError_t launch16(const XArgs &a, hipStream_t st) {
+    const int64_t waves = (int64_t)a.nregions * a.K * a.nsplit;
+    const int grid = (int)(8 * ((waves + 31) / 32));
+    hipLaunchKernelGGL((xstage16_kernel<RB, KIND>), dim3(grid), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_xstage16(int rb, int kind, const XArgs &a, hipStream_t st) {
+    if (kind == kDiag) {
+        switch (rb) {
+            case 1: return launch16<1, kDiag>(a, st);
+            case 2: return launch16<2, kDiag>(a, st);
+            case 3: return launch16<3, kDiag>(a, st);
+        }
+    } else if (kind == kOffDiag) {
+        switch (rb) {
+            case 1: return launch16<1, kOffDiag>(a, st);
+            case 2: return launch16<2, kOffDiag>(a, st);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_xstage(int prec, int rb, int kind, const XArgs &a, hipStream_t st) {
+    if (prec == kINT16) return launch_xstage16(rb, kind, a, st);
     switch (prec) {
         case kFP32: return launch_p<kFP32>(rb, kind, a, st);
         case kFP16: return launch_p<kFP16>(rb, kind, a, st);

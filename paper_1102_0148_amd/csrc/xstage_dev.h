@@ -411,5 +411,100 @@ __device__ __forceinline__ void x_group(const XArgs &a, int unit, uint4 *const (
         }
 }
 
+// ------------------------------------------------------------------ int16
+// The 16-bit form (the paper's short complex type) on the int8 MFMA.  Each
+// value is q = 255 h + l with digits h, l in [-127, 127], so
+//     sum q_a q_b = 65025 sum h_a h_b + 255 sum (h_a l_b + l_a h_b) + sum l_a l_b,
+// every digit sum exact in int32, combined exactly at the end.  A record
+// holds 4 spectra as [h re x4][h im x4][l re x4][l im x4]; one MFMA operand
+// (16 bytes per lane) takes the digits of two consecutive records, so a step
+// covers 8 records (two k-blocks) and lane group g reads records 2g, 2g + 1.
+// Digit negation is exact, so Q = [im | -re] is formed digit-wise as for
+// int8.  Six accumulators per block pair: Re and Im of (hh, hl + lh, ll).
+template <int RB, bool DIAG>
+__device__ __forceinline__ void x_wave16(const XArgs &a, int wave) {
+    const int lane = threadIdx.x & 63;
+    if (wave >= a.nregions * a.K * a.nsplit) return;
+    const int reg = wave % a.nregions;
+    const int rest = wave / a.nregions;
+    const int f = rest % a.K;
+    const int sp = rest / a.K;
+    const int I0 = a.regions[reg].x, J0 = a.regions[reg].y;
+    // steps of two k-blocks (a.nkb is even for this form)
+    const int nst = a.nkb / 2;
+    const int st0 = (int)((int64_t)sp * nst / a.nsplit);
+    const int st1 = (int)((int64_t)(sp + 1) * nst / a.nsplit);
+    i32x4 rhh[RB][RB], rx[RB][RB], rll[RB][RB], ihh[RB][RB], ix[RB][RB], ill[RB][RB];
+#pragma unroll
+    for (int I = 0; I < RB; ++I)
+#pragma unroll
+        for (int J = 0; J < RB; ++J)
+            rhh[I][J] = rx[I][J] = rll[I][J] = ihh[I][J] = ix[I][J] = ill[I][J] = i32x4{0, 0, 0, 0};
+    // lane (row r, group g): records tq = 8 step + 2 g and + 1 of antenna 16 I + r
+    const uint4 *base = a.spec + (int64_t)f * kTQB * a.a_pad + (2 * (lane >> 4)) * a.a_pad + (lane & 15);
+    const int64_t bstride = (int64_t)a.K * kTQB * a.a_pad;
+    auto mm = [](i32x4 &acc, uint4 x, uint4 y) {
+        const i32x4 av = {(int)x.x, (int)x.y, (int)x.z, (int)x.w};
+        const i32x4 bv = {(int)y.x, (int)y.y, (int)y.z, (int)y.w};
+        acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(av, bv, acc, 0, 0, 0);
+    };
+    for (int st = st0; st < st1; ++st) {
+        // step st: time block st / 2, records 8 (st % 2) .. + 7
+        const uint4 *rec = base + (st >> 1) * bstride + (st & 1) * 8 * a.a_pad;
+        uint4 ph[RB], pl[RB], qh[RB], ql[RB], ch[RB], cl[RB];
+#pragma unroll
+        for (int I = 0; I < RB; ++I) {
+            const uint4 r0 = rec[(I0 + I) * 16], r1 = rec[(I0 + I) * 16 + a.a_pad];
+            ph[I] = make_uint4(r0.x, r0.y, r1.x, r1.y);
+            pl[I] = make_uint4(r0.z, r0.w, r1.z, r1.w);
+            qh[I] = make_uint4(r0.y, neg_i8x4(r0.x), r1.y, neg_i8x4(r1.x));
+            ql[I] = make_uint4(r0.w, neg_i8x4(r0.z), r1.w, neg_i8x4(r1.z));
+        }
+        if constexpr (!DIAG) {
+#pragma unroll
+            for (int J = 0; J < RB; ++J) {
+                const uint4 r0 = rec[(J0 + J) * 16], r1 = rec[(J0 + J) * 16 + a.a_pad];
+                ch[J] = make_uint4(r0.x, r0.y, r1.x, r1.y);
+                cl[J] = make_uint4(r0.z, r0.w, r1.z, r1.w);
+            }
+        }
+#pragma unroll
+        for (int I = 0; I < RB; ++I)
+#pragma unroll
+            for (int J = 0; J < RB; ++J) {
+                if (DIAG && J < I) continue;
+                const uint4 bh = DIAG ? ph[J] : ch[J], bl = DIAG ? pl[J] : cl[J];
+                mm(rhh[I][J], ph[I], bh);
+                mm(rx[I][J], ph[I], bl);
+                mm(rx[I][J], pl[I], bh);
+                mm(rll[I][J], pl[I], bl);
+                mm(ihh[I][J], qh[I], bh);
+                mm(ix[I][J], qh[I], bl);
+                mm(ix[I][J], ql[I], bh);
+                mm(ill[I][J], ql[I], bl);
+            }
+    }
+    // accumulator element v of lane l is row 4*(l/16)+v, column l%16
+    const int64_t obase = ((int64_t)sp * a.K + f) * a.nb;
+    double2 *out = reinterpret_cast<double2 *>(a.partial);
+#pragma unroll
+    for (int I = 0; I < RB; ++I)
+#pragma unroll
+        for (int J = 0; J < RB; ++J) {
+            if (DIAG && J < I) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int ia = (I0 + I) * 16 + 4 * (lane >> 4) + v;
+                const int ib = (J0 + J) * 16 + (lane & 15);
+                if (ia < a.N && ib < a.N && ia <= ib) {
+                    const int bl = ia * a.N - ia * (ia - 1) / 2 + (ib - ia);
+                    const int64_t re = 65025ll * rhh[I][J][v] + 255ll * rx[I][J][v] + (int64_t)rll[I][J][v];
+                    const int64_t im = 65025ll * ihh[I][J][v] + 255ll * ix[I][J][v] + (int64_t)ill[I][J][v];
+                    out[obase + bl] = make_double2((double)re, ia == ib ? 0.0 : (double)im);
+                }
+            }
+        }
+}
+
 }  // namespace
 }  // namespace corr

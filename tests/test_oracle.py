@@ -448,3 +448,39 @@ def test_scales_over_received_spectra(orc):
     kept = np.delete(spec[:W], lost, axis=0)
     np.testing.assert_allclose(orc.scales_n(zeroed, W, W - len(lost)), orc.scales(kept, W - len(lost)),
                                rtol=1e-6)
+
+
+# ------------------------------------------------------------------- int16
+
+def test_quantise16_rounding_and_saturation(orc):
+    """Ties to even, symmetric clamp at +-32512 (= 255 * 127 + 127)."""
+    x = np.array([2.5, 3.5, -2.5, -3.5, 0.49, 32512.4, 32512.6, 40000.0, -1e9, 1e9, -0.5])
+    spec = np.zeros((1, 1, x.size), dtype=np.complex128)
+    spec[0, 0, :] = x + 1j * (-x)
+    q = orc.quantise16(spec, np.ones((1, x.size), dtype=np.float32))
+    want = np.array([2, 4, -2, -4, 0, 32512, 32512, 32512, -32512, 32512, 0])
+    np.testing.assert_array_equal(q[0, 0, :, 0], want)
+    np.testing.assert_array_equal(q[0, 0, :, 1], -want)
+
+
+def test_cmac_i64_16_exact(orc):
+    """Against numpy's int64 sums, extreme codes included."""
+    rng = np.random.default_rng(11)
+    S, N, K = 9, 5, 8
+    q = rng.integers(-32512, 32513, size=(S, N, K, 2)).astype(np.int16)
+    q[0] = 32512
+    q[1, :, :, 1] = -32512
+    v = orc.cmac_i64_16(q, full=True)
+    re, im = q[..., 0].astype(np.int64), q[..., 1].astype(np.int64)
+    vr = np.einsum("sak,sbk->abk", re, re) + np.einsum("sak,sbk->abk", im, im)
+    vi = np.einsum("sak,sbk->abk", im, re) - np.einsum("sak,sbk->abk", re, im)
+    np.testing.assert_array_equal(v[..., 0], vr)
+    np.testing.assert_array_equal(v[..., 1], vi)
+
+
+def test_scales16_are_256_times_int8_scales(orc):
+    """32512 = 256 * 127, a power of two apart: the int16 rule's scales are
+    exactly 256 times the int8 rule's."""
+    rng = np.random.default_rng(12)
+    spec = rng.standard_normal((30, 3, 16)) * 40 + 1j * rng.standard_normal((30, 3, 16)) * 40
+    np.testing.assert_array_equal(orc.scales_n(spec, 20, 20, 32512.0), 256 * orc.scales(spec, 20))
