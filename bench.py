@@ -311,8 +311,8 @@ def main():
                     help="also run a plain 1 GiB device copy (scale reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the time-domain sharding across GPUs is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(time-domain sharding across GPUs is a design note, not code)", file=sys.stderr)
         sys.exit(2)
 
     import torch
