@@ -27,10 +27,13 @@ ARCH = "gfx950"
 LDS_LIMIT = 160 * 1024
 SPLITS = (4, 8, 12, 16, 24, 32, 48, 64)
 MAX_SPECTRA_PER_PARTIAL = 2048   # float partials stay short (accuracy)
+# spectra one partial may sum, per form: float partials stay short for
+# accuracy; int16 digit sums must stay exact in int32; int8 sums always are
+PARTIAL_LIMIT = {"fp32": MAX_SPECTRA_PER_PARTIAL, "fp16": MAX_SPECTRA_PER_PARTIAL, "int16": 16384, "int8": None}
 
 
 def record_times(prec: str) -> int:
-    return {"fp32": 2, "fp16": 4, "int8": 8}[prec]
+    return {"fp32": 2, "fp16": 4, "int8": 8, "int16": 4}[prec]
 
 
 def f_lds_bytes(K: int, prec: str, group: int) -> int:
@@ -53,7 +56,7 @@ def candidates(N: int, K: int, S: int, prec: str) -> List[dict]:
     out = []
     for chunk in chunks:
         for s in SPLITS:
-            if prec != "int8" and chunk / s > MAX_SPECTRA_PER_PARTIAL:
+            if PARTIAL_LIMIT[prec] and chunk / s > PARTIAL_LIMIT[prec]:
                 continue
             for g in groups:
                 out.append({"chunk_spectra": chunk, "x_splits": s, "f_group": g})
@@ -124,7 +127,7 @@ def tune_batch_job(N: int, K: int, S: int, prec: str, log=print) -> Tuple[dict, 
     x = synth.packed(synth.recipe_plain(N=N, two_k=2 * K, seed=12), 0, S, device="cuda").contiguous()
     best = None
     for s in SPLITS:
-        if prec != "int8" and S / s > MAX_SPECTRA_PER_PARTIAL:
+        if PARTIAL_LIMIT[prec] and S / s > PARTIAL_LIMIT[prec]:
             continue
         b = corr.Batch([(N, K, S, prec)], tiles={0: {"x_splits": s}}, mode="persistent")
         try:
@@ -150,7 +153,7 @@ def tune_batch_job(N: int, K: int, S: int, prec: str, log=print) -> Tuple[dict, 
 def main(argv: Optional[Iterable[str]] = None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=TABLE)
-    ap.add_argument("--single", default="44:256:65536:fp32,44:256:65536:fp16,44:256:65536:int8,"
+    ap.add_argument("--single", default="44:256:65536:fp32,44:256:65536:fp16,44:256:65536:int8,44:256:65536:int16,"
                                         "256:512:16384:fp32,256:512:16384:int8")
     ap.add_argument("--batch", default="8:128:16384,12:256:16384,16:512:16384,24:256:16384,"
                                        "32:1024:16384,44:256:16384,64:512:16384,96:256:16384")

@@ -349,10 +349,10 @@ def round_up(x, m):
     return (x + m - 1) // m * m
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp16", "int8"])
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "int8", "int16"])
 def test_every_autotuner_candidate_passes_parity(prec):
     """Each tile choice the autotuner may pick: float forms within tolerance
-    of the oracle, int8 identical to every other candidate."""
+    of the oracle, int8 and int16 identical to every other candidate."""
     from paper_1102_0148_amd import tune
     N, K, S = 44, 256, 300
     packed = _packed(synth.recipe_plain(N=N, two_k=2 * K, seed=21), S)
@@ -362,7 +362,7 @@ def test_every_autotuner_candidate_passes_parity(prec):
     first = None
     for t in cands:
         _, raw = run(N, K, S, packed, precision=corr.PRECISIONS[prec], tiles=t)
-        if prec == "int8":
+        if prec in ("int8", "int16"):
             if first is None:
                 first = raw
             else:

@@ -6,15 +6,17 @@ from paper_1102_0148_amd import tune
 
 def test_candidates_respect_limits():
     for (N, K, S, prec) in [(44, 256, 65536, "fp32"), (44, 256, 65536, "int8"), (32, 1024, 16384, "fp16"),
-                            (256, 512, 16384, "fp32"), (8, 128, 3, "int8")]:
+                            (256, 512, 16384, "fp32"), (8, 128, 3, "int8"), (44, 256, 65536, "int16")]:
         c = tune.candidates(N, K, S, prec)
         assert c, (N, K, S, prec)
         for t in c:
             assert t["chunk_spectra"] % 64 == 0 and t["chunk_spectra"] <= (S + 63) // 64 * 64
             assert tune.f_lds_bytes(K, prec, t["f_group"]) <= tune.LDS_LIMIT
             assert 1 <= t["x_splits"] <= 64
-            if prec != "int8":
+            if prec in ("fp32", "fp16"):
                 assert t["chunk_spectra"] / t["x_splits"] <= tune.MAX_SPECTRA_PER_PARTIAL
+            if prec == "int16":
+                assert t["chunk_spectra"] / t["x_splits"] <= 16384
 
 
 def test_table_lookup(tmp_path):
