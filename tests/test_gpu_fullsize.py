@@ -73,3 +73,72 @@ def test_full_integration_sampled_baselines(prec):
     qmax = 127.0 if prec == "int8" else 32512.0
     W = corr.CORR_CALIB_SPECTRA
     np.testing.assert_allclose(scales[ANTS], oracle.scales_n(spec, W, W, qmax), rtol=1e-5)
+
+
+def _sel_codes_n(buf, precision, N_, K_, S_, ants):
+    """As _sel_codes for another shape."""
+    tg = corr.record_times(precision)
+    a_pad = corr.a_pad_of(N_)
+    ntq = ((S_ + tg - 1) // tg + corr.TQB - 1) // corr.TQB * corr.TQB
+    rec = np.asarray(buf)[: ntq * K_ * a_pad * 16].reshape(ntq // corr.TQB, K_, corr.TQB, a_pad, 16)
+    sel = np.ascontiguousarray(rec[:, :, :, ants, :]).view(np.int8)
+    v = sel.reshape(ntq // corr.TQB, K_, corr.TQB, len(ants), 2, tg)
+    v = np.transpose(v, (0, 2, 5, 3, 1, 4)).reshape(ntq * tg, len(ants), K_, 2)[:S_]
+    return np.ascontiguousarray(v)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "int8"])
+def test_large_n_full_size_sampled_baselines(prec):
+    """N = 256, 1024-point, 16384 spectra with three delayed sources, in the
+    benchmark's launch configuration: antennas from different 64-antenna
+    region rows, so the sampled baselines fall in diagonal and off-diagonal
+    regions (LDS-staged groups for int8)."""
+    N_, K_, S_ = 256, 512, 16384
+    ants = [0, 37, 70, 130, 200, 255]
+    packed = synth.packed(synth.recipe_sources(N=N_, two_k=2 * K_, seed=4), 0, S_, device="cuda").contiguous()
+    c = corr.Correlator(N_, K_, S_, precision=prec, tiles="auto")
+    print(f"\n[large N] {prec} tiles {c.tiles()}", flush=True)
+    c.process(packed)
+    spec = oracle.spectra(packed[:, ants, :].cpu().numpy(), S_, len(ants), K_)
+    rows = [oracle.baseline_index(N_, a, b) for i, a in enumerate(ants) for b in ants[i:]]
+    if prec == "fp32":
+        raw = raw_to_complex(c.read_cps_raw())
+        ref = oracle.cmac_f64(spec)
+        err = coef_error(raw[rows], ref, len(ants))
+        print(f"  coefficient error {err:.3g}", flush=True)
+        assert err <= TOL[corr.CORR_FP32]
+        return
+    buf, n = c.debug_read_spectra()
+    raw = c.read_cps_raw()
+    q = _sel_codes_n(buf, corr.CORR_INT8, N_, K_, S_, ants)
+    np.testing.assert_array_equal(raw[rows], oracle.cmac_i64(q).astype(np.float64))
+
+
+def test_batch_full_size_sampled_baselines():
+    """The 12-job batch of the benchmark (16384 spectra per job, int8 and
+    fp32 alternating), in its default mode: every job's baselines among its
+    first, a middle and its last antenna against the oracle."""
+    recipes = synth.batch_jobs(12, seed=3)
+    S_ = 16384
+    jobs = [(r.N, r.K, S_, "fp32" if j % 2 == 0 else "int8") for j, r in enumerate(recipes)]
+    xs = [synth.packed(r, 0, S_, device="cuda").contiguous() for r in recipes]
+    b = corr.Batch(jobs, tiles="auto")
+    b.process(xs)
+    for j, (r, (N_, K_, _, prec)) in enumerate(zip(recipes, jobs)):
+        ants = sorted({0, N_ // 2, N_ - 1})
+        raw = b.read_cps_raw(j)
+        spec = oracle.spectra(xs[j][:, ants, :].cpu().numpy(), S_, len(ants), K_)
+        rows = [oracle.baseline_index(N_, a, c) for i, a in enumerate(ants) for c in ants[i:]]
+        if prec == "fp32":
+            err = coef_error(raw_to_complex(raw)[rows], oracle.cmac_f64(spec), len(ants))
+            print(f"\n  job {j} N={N_} K={K_} fp32: {err:.3g}", flush=True)
+            assert err <= TOL[corr.CORR_FP32]
+        else:
+            # exact integers in quantised units, and close to float64 once de-scaled
+            assert np.array_equal(raw[rows], np.round(raw[rows]))
+            sc = b.read_scales(j)[ants]
+            den = np.array([sc[i].astype(np.float64) * sc[k] for i in range(len(ants)) for k in range(i, len(ants))])
+            v = raw_to_complex(raw)[rows] / den
+            err = coef_error(v, oracle.cmac_f64(spec), len(ants))
+            print(f"\n  job {j} N={N_} K={K_} int8 de-scaled: {err:.3g}", flush=True)
+            assert err <= 3e-2
