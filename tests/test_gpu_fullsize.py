@@ -69,7 +69,7 @@ def test_full_integration_sampled_baselines(prec):
     qref = oracle.quantise(spec, scales[ANTS]) if prec == "int8" else oracle.quantise16(spec, scales[ANTS])
     diff = q.astype(np.int32) - qref.astype(np.int32)
     assert np.max(np.abs(diff)) <= 1
-    assert np.mean(diff != 0) <= 1e-3
+    assert np.mean(diff != 0) <= (1e-3 if prec == "int8" else 5e-3)
     qmax = 127.0 if prec == "int8" else 32512.0
     W = corr.CORR_CALIB_SPECTRA
     np.testing.assert_allclose(scales[ANTS], oracle.scales_n(spec, W, W, qmax), rtol=1e-5)

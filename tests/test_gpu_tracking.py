@@ -72,27 +72,35 @@ def test_tracked_long_integration_large_phases():
     assert coef_error(raw, ref, N) <= TOL[corr.CORR_FP32]
 
 
-def test_tracked_int8():
+@pytest.mark.parametrize("prec", ["int8", "int16"])
+def test_tracked_integer_forms(prec):
     """Scales as without tracking (a rotation keeps |X|); codes within one of
     the oracle's rule on the oracle's rotated spectra; the X-stage exact on
     the GPU's own codes."""
     N, K, S = 44, 256, 200
+    code = corr.PRECISIONS[prec]
+    qmax = 127.0 if prec == "int8" else 32512.0
+    quantise = oracle.quantise if prec == "int8" else oracle.quantise16
+    cmac = oracle.cmac_i64 if prec == "int8" else oracle.cmac_i64_16
     packed = synth.packed(synth.recipe_plain(N=N, two_k=2 * K, seed=12), 0, S).contiguous()
     m = _model(N, seed=5)
-    c = corr.Correlator(N, K, S, precision="int8", tiles=dict(chunk_spectra=_round_up(S, 64)))
+    c = corr.Correlator(N, K, S, precision=prec, tiles=dict(chunk_spectra=_round_up(S, 64)))
     c.set_tracking(**m)
     c.process(packed.cuda())
     buf, n = c.debug_read_spectra()
     scales = c.read_scales()
     raw = c.read_cps_raw()
-    q_gpu = corr.records_to_spectra(buf, corr.CORR_INT8, N, K, S)
-    np.testing.assert_array_equal(raw, oracle.cmac_i64(q_gpu).astype(np.float64))
+    q_gpu = corr.records_to_spectra(buf, code, N, K, S)
+    np.testing.assert_array_equal(raw, cmac(q_gpu).astype(np.float64))
     spec = oracle.spectra(packed.numpy(), S, N, K)
-    np.testing.assert_allclose(scales, oracle.scales(spec, min(S, corr.CORR_CALIB_SPECTRA)), rtol=1e-5)
-    q_ref = oracle.quantise(oracle.track(spec, **m), scales)
+    W = min(S, corr.CORR_CALIB_SPECTRA)
+    np.testing.assert_allclose(scales, oracle.scales_n(spec, W, W, qmax), rtol=1e-5)
+    q_ref = quantise(oracle.track(spec, **m), scales)
     diff = q_gpu.astype(np.int32) - q_ref.astype(np.int32)
     assert np.max(np.abs(diff)) <= 1
-    assert np.mean(diff != 0) <= 1e-3
+    # int16 steps are 256 times finer, so the same float difference between
+    # the GPU's and the oracle's spectra reaches a rounding tie more often
+    assert np.mean(diff != 0) <= (1e-3 if prec == "int8" else 5e-3)
 
 
 def test_tracking_undoes_circular_delays():
