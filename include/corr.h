@@ -7,7 +7,11 @@
  * K channels (the F-stage), the spectra are turned channel-major, and every
  * pair is cross-multiplied and accumulated over the spectra of an integration
  * (the X-stage).  Each time tile's partial result is added into a float64
- * integration buffer.
+ * integration buffer.  Around that path: the X-stage arithmetic (float32,
+ * half, or spectra requantised to 8 or 16 bits), per-antenna delay and phase
+ * tracking applied before accumulation, assembly of an integration from
+ * self-contained frames that may be lost, repeated or reordered, and batches
+ * of uneven jobs replayed from one HIP graph.
  *
  * Conventions common to every entry point:
  *   - Input frames: byte layout [spectrum][antenna][K bytes]; one antenna
@@ -217,7 +221,7 @@ int corr_debug_read_spectra(corr_handle h, void *out, int *n_spectra);
  * each stage; they are read, which waits for them, only here).  */
 typedef struct {
     int64_t spectra_accumulated; /* spectra in the integration buffer */
-    int64_t int8_saturated;      /* components clamped to +-127 (INT8) */
+    int64_t int8_saturated;      /* components clamped to the largest code (INT8: +-127, INT16: +-32512) */
     int precision;
     int chunk_spectra, x_splits, f_group;
     double ms_calib, ms_f, ms_x, ms_dump; /* 0 unless timing is on */
