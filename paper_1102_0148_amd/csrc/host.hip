@@ -218,11 +218,13 @@ int default_splits(const corr_ctx *h) {
     const int64_t waves_per_split = (int64_t)n_regions(h) * h->K;
     int s = (int)((4096 + waves_per_split - 1) / waves_per_split);
     s = std::max(1, std::min(64, s));
-    // fp32 / fp16 partials cover at most ~2048 spectra each; int16 digit
-    // sums stay exact in int32 over up to 16384
+    // spectra per partial: fp32 at most 4096 and fp16 16384 (accuracy), int16
+    // 16384 (exact int32 digit sums)
     const int chunk = h->tiles.chunk_spectra;
-    if (h->prec == kFP32 || h->prec == kFP16) s = std::max(s, std::min(64, (chunk + 2047) / 2048));
-    if (h->prec == kINT16) s = std::max(s, (chunk + kI16SplitSpectra - 1) / kI16SplitSpectra);
+    const int cap = h->prec == kFP32 ? kF32SplitSpectra
+                  : h->prec == kFP16 ? kF16SplitSpectra
+                  : h->prec == kINT16 ? kI16SplitSpectra : 0;
+    if (cap) s = std::max(s, std::min(64, (chunk + cap - 1) / cap));
     return s;
 }
 

@@ -13,10 +13,8 @@ def test_candidates_respect_limits():
             assert t["chunk_spectra"] % 64 == 0 and t["chunk_spectra"] <= (S + 63) // 64 * 64
             assert tune.f_lds_bytes(K, prec, t["f_group"]) <= tune.LDS_LIMIT
             assert 1 <= t["x_splits"] <= 64
-            if prec in ("fp32", "fp16"):
-                assert t["chunk_spectra"] / t["x_splits"] <= tune.MAX_SPECTRA_PER_PARTIAL
-            if prec == "int16":
-                assert t["chunk_spectra"] / t["x_splits"] <= 16384
+            if tune.PARTIAL_LIMIT[prec]:
+                assert t["chunk_spectra"] / t["x_splits"] <= tune.PARTIAL_LIMIT[prec]
 
 
 def test_table_lookup(tmp_path):
