@@ -21,11 +21,12 @@ constexpr int kI16Max = 32512;
 // cross sum adds 4 digit products per spectrum: 4 * 16384 * 127^2 < 2^31)
 constexpr int kI16SplitSpectra = 16384;
 // spectra one float partial may sum: the fp32 form's three-product
-// combination Im = P3 - P1 + P2 cancels, and its error grows past the stated
-// bound beyond about 4096 spectra (measured: 2e-6 at 4096, 1e-4 at 8192, in
-// coefficient units); the fp16 form's error is its half-precision spectra's
-// at any length up to 16384
-constexpr int kF32SplitSpectra = 4096;
+// combination Im = P3 - P1 + P2 cancels, so its error grows with the length
+// of the sum, faster with stronger correlations (in coefficient units, 2e-6
+// at 4096 for a weak common signal at N = 44, but 6e-5 at 4096 for three
+// delayed sources at N = 256); the fp16 form's error is its half-precision
+// spectra's at any length up to 16384
+constexpr int kF32SplitSpectra = 2048;
 constexpr int kF16SplitSpectra = 16384;
 
 // A spectra record is 16 bytes: TG consecutive spectra of one (channel,

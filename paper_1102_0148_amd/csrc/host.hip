@@ -218,7 +218,7 @@ int default_splits(const corr_ctx *h) {
     const int64_t waves_per_split = (int64_t)n_regions(h) * h->K;
     int s = (int)((4096 + waves_per_split - 1) / waves_per_split);
     s = std::max(1, std::min(64, s));
-    // spectra per partial: fp32 at most 4096 and fp16 16384 (accuracy), int16
+    // spectra per partial: fp32 at most 2048 and fp16 16384 (accuracy), int16
     // 16384 (exact int32 digit sums)
     const int chunk = h->tiles.chunk_spectra;
     const int cap = h->prec == kFP32 ? kF32SplitSpectra

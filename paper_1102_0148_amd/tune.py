@@ -29,7 +29,7 @@ SPLITS = (4, 8, 12, 16, 24, 32, 48, 64)
 # spectra one partial may sum, per form: fp32 partials stay short for
 # accuracy (its three-product form cancels), fp16's error is its spectra's up
 # to 16384; int16 digit sums must stay exact in int32; int8 sums always are
-PARTIAL_LIMIT = {"fp32": 4096, "fp16": 16384, "int16": 16384, "int8": None}
+PARTIAL_LIMIT = {"fp32": 2048, "fp16": 16384, "int16": 16384, "int8": None}
 
 
 def record_times(prec: str) -> int:

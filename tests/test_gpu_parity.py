@@ -3,7 +3,7 @@ same seeded inputs.  Needs an MI355X and the built libcorr.so.
 
 Tolerances (coefficient units, |V - V64| / sqrt(V64_aa V64_bb), the error a
 visibility carries relative to the noise power of its two antennas):
-  fp32: 1e-5    float spectra and float MFMA sums over <= 4096 spectra per
+  fp32: 1e-5    float spectra and float MFMA sums over <= 2048 spectra per
                 partial; the float FFT alone is good to ~1e-7 per bin
   fp16: 2e-3    half-precision spectra (2^-11 relative) dominate
   int8: exact   against the integer oracle on the same quantised spectra
