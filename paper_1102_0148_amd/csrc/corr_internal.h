@@ -47,6 +47,12 @@ __host__ __device__ inline int64_t rec_index(int c, int tq, int a, int K, int a_
     return (((int64_t)(tq / kTQB) * K + c) * kTQB + (tq % kTQB)) * a_pad + a;
 }
 
+// Word 3 of a raw buffer resource on this target (no format conversion, no
+// swizzle): stores at offsets past the resource's byte range are dropped.
+constexpr int kBufferRsrcFlags = 0x00020000;
+// Bytes allocated past the last record time block (see the F-stage's stores).
+constexpr size_t kSpecSlack = 256;
+
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
 // Orders this wavefront's LDS writes before its later LDS reads.

@@ -457,6 +457,20 @@ __device__ __forceinline__ void tile_records(const FArgs &args, int tq, int g,
     using Sh = FShape<M, PREC, GA, false>;
     constexpr int TS = Sh::TS, SLOT = Sh::SLOT, NTASK = Sh::NTASK, TPT = Sh::TPT;
     const int tid = threadIdx.x;
+    // The tile's records lie in one time block of `span` bytes, addressed
+    // through a buffer resource.  Padding antennas that fill whole 128-byte
+    // lines (8 records, from N rounded up to 8) are never stored: the buffer
+    // is cleared when it is allocated, so their records stay zero.  Their
+    // stores go to offset `span`, past the resource's range, where the
+    // hardware drops them; no branch is needed (and the allocation has slack
+    // beyond the last block, so that offset lies inside it in any case).
+    // Padding that shares a line with real antennas is stored (as zeros): a
+    // half-written line costs a read of the line to merge it.
+    const int n_store = (args.N + 7) & ~7;
+    const int tqb = __builtin_amdgcn_readfirstlane(tq / kTQB);
+    const uint32_t span = (uint32_t)M * kTQB * (uint32_t)args.a_pad * kRecordBytes;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        args.spec + (int64_t)tqb * M * kTQB * args.a_pad, 0, (int)span, kBufferRsrcFlags);
     tile_ffts<M, Sh::NF, Sh::ROUNDS>(cur, zbuf, bbuf, k.ptw);
     __syncthreads();
 #pragma unroll
@@ -480,8 +494,12 @@ __device__ __forceinline__ void tile_records(const FArgs &args, int tq, int g,
         }
         const uint4 rlo = make_record<PREC, TS>(lr, li, slo[it], wsat);
         const uint4 rhi = make_record<PREC, TS>(hr, hi, shi[it], wsat);
-        args.spec[rec_index(clo, tq, a, M, args.a_pad)] = rlo;
-        args.spec[rec_index(chi, tq, a, M, args.a_pad)] = rhi;
+        const uint32_t row = (uint32_t)(tq % kTQB) * args.a_pad + a;
+        const bool stored = a < n_store;
+        const uint32_t olo = stored ? ((uint32_t)clo * kTQB * args.a_pad + row) * kRecordBytes : span;
+        const uint32_t ohi = stored ? ((uint32_t)chi * kTQB * args.a_pad + row) * kRecordBytes : span;
+        __builtin_amdgcn_raw_buffer_store_b128(u32x4{rlo.x, rlo.y, rlo.z, rlo.w}, rs, olo, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(u32x4{rhi.x, rhi.y, rhi.z, rhi.w}, rs, ohi, 0, 0);
     }
 }
 

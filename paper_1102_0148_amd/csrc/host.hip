@@ -255,8 +255,10 @@ int plan(corr_ctx *h) {
     }
     h->ntq_buf = round_up((chunk + h->TG - 1) / h->TG, kTQB);
     h->spec_bytes = (size_t)h->K * h->ntq_buf * h->a_pad * kRecordBytes;
-    HIP_TRY(hipMalloc(&h->spec, h->spec_bytes), "hipMalloc(spectra chunk)");
-    HIP_TRY(hipMemset(h->spec, 0, h->spec_bytes), "hipMemset(spectra chunk)");
+    // cleared once: records of padding antennas in lines of their own are
+    // never written again
+    HIP_TRY(hipMalloc(&h->spec, h->spec_bytes + kSpecSlack), "hipMalloc(spectra chunk)");
+    HIP_TRY(hipMemset(h->spec, 0, h->spec_bytes + kSpecSlack), "hipMemset(spectra chunk)");
     HIP_TRY(hipMalloc(&h->partial, (size_t)h->tiles.x_splits * h->K * h->nb * (h->prec == kINT16 ? 16 : 8)),
             "hipMalloc(partials)");
     if (is_quant(h->prec)) {

@@ -74,7 +74,9 @@ def lookup(N: int, K: int, S: int, prec: str, batch: bool = False, path: str = T
     return load_table(path).get(key(N, K, S, prec, batch))
 
 
-def _time_single(corr, torch, N, K, S, prec, tiles, x, reps=3, warm=1) -> float:
+def _time_single(corr, torch, N, K, S, prec, tiles, x, reps=3, warm=1) -> Dict[str, float]:
+    """Per-integration stage times (ms) of one tile choice: F-stage, X-stage
+    plus dump, calibration and their total."""
     c = corr.Correlator(N, K, S, precision=prec, tiles=tiles)
     dst = torch.empty(c.nb * K * 2, dtype=torch.float64, device="cuda")
     try:
@@ -86,47 +88,72 @@ def _time_single(corr, torch, N, K, S, prec, tiles, x, reps=3, warm=1) -> float:
             c.process(x)
             c.read_cps_async(dst)
         st = c.stats()
-        return (st["ms_f"] + st["ms_x"] + st["ms_dump"] + st["ms_calib"]) / reps
+        t = {"f": st["ms_f"] / reps, "x": (st["ms_x"] + st["ms_dump"]) / reps, "calib": st["ms_calib"] / reps}
+        t["total"] = t["f"] + t["x"] + t["calib"]
+        return t
     finally:
         c.close()
         del dst
         torch.cuda.empty_cache()
 
 
+def _median(v: List[float]) -> float:
+    v = sorted(v)
+    return v[len(v) // 2] if len(v) % 2 else 0.5 * (v[len(v) // 2 - 1] + v[len(v) // 2])
+
+
+def _rounds(corr, torch, N, K, S, prec, x, cands, stage, rounds=3, reps=4, log=print) -> List[Tuple[dict, float]]:
+    """Median of `stage` time over `rounds` passes that time every candidate in
+    turn, so a drift of the clock during the run falls on all of them alike."""
+    seen: Dict[str, List[float]] = {}
+    for r in range(rounds):
+        for t in cands:
+            ms = _time_single(corr, torch, N, K, S, prec, t, x, reps=reps, warm=1)[stage]
+            seen.setdefault(json.dumps(t, sort_keys=True), []).append(ms)
+            log(f"  {prec} N={N} K={K} {t} {stage} {ms:.4f} ms (round {r})")
+    return [(json.loads(k), _median(v)) for k, v in seen.items()]
+
+
 def tune_single(N: int, K: int, S: int, prec: str, log=print) -> Tuple[dict, float, List[Tuple[dict, float]]]:
+    """Stage 1 times every (chunk, splits) at the default F group; stage 2
+    picks the group by the F-stage time alone (the only stage it changes),
+    timing the groups in turn at the best chunk; stage 3 times the four best
+    (chunk, splits) pairs of stage 1 with that group in turn and keeps the
+    lowest median total (ties as in `pick`)."""
     import torch
     import paper_1102_0148_amd as corr
     import synth
     x = synth.packed(synth.recipe_plain(N=N, two_k=2 * K, seed=11), 0, S, device="cuda").contiguous()
-    results = []
-    # stage 1: chunk and splits at the default group; stage 2: groups at the best
-    base_group = None
     cands = candidates(N, K, S, prec)
-    default_groups = {c["f_group"] for c in cands}
+    groups = sorted({c["f_group"] for c in cands})
     fpr = 256 // (K // 16)
     dg = max(1, fpr // record_times(prec))
-    base_group = dg if dg in default_groups else min(default_groups)
+    base_group = dg if dg in groups else min(groups)
+    results = []
     for t in [c for c in cands if c["f_group"] == base_group]:
-        ms = _time_single(corr, torch, N, K, S, prec, t, x)
+        ms = _time_single(corr, torch, N, K, S, prec, t, x)["total"]
         results.append((t, ms))
         log(f"  {prec} N={N} K={K} {t} {ms:.4f} ms")
-    # stage 2: every group for the three best (chunk, splits) pairs, whose
-    # times are often within the noise of one another
-    top = sorted(results, key=lambda r: r[1])[:3]
-    for b, _ in top:
-        for t in [c for c in cands if c["chunk_spectra"] == b["chunk_spectra"] and
-                  c["x_splits"] == b["x_splits"] and c["f_group"] != base_group]:
-            ms = _time_single(corr, torch, N, K, S, prec, t, x)
-            results.append((t, ms))
-            log(f"  {prec} N={N} K={K} {t} {ms:.4f} ms")
-    # stage 3: the four best again, with more repetitions
-    final = []
-    for t, _ in sorted(results, key=lambda r: r[1])[:4]:
-        ms = _time_single(corr, torch, N, K, S, prec, t, x, reps=8, warm=2)
-        final.append((t, ms))
-        log(f"  {prec} N={N} K={K} {t} {ms:.4f} ms (final)")
-    best, best_ms = min(final, key=lambda r: r[1])
+    top = [t for t, _ in sorted(results, key=lambda r: r[1])[:4]]
+    chunk, splits = top[0]["chunk_spectra"], top[0]["x_splits"]
+    by_f = _rounds(corr, torch, N, K, S, prec, x,
+                   [{"chunk_spectra": chunk, "x_splits": splits, "f_group": g} for g in groups], "f", log=log)
+    group = min(by_f, key=lambda r: r[1])[0]["f_group"]
+    final = _rounds(corr, torch, N, K, S, prec, x, [dict(t, f_group=group) for t in top], "total", log=log)
+    best, best_ms = pick(final)
     return best, best_ms, results + final
+
+
+TIE = 0.01
+
+
+def pick(timed: List[Tuple[dict, float]]) -> Tuple[dict, float]:
+    """The fastest tile choice, except that choices within TIE (relative) of
+    it count as ties, which go to the fewest chunks, then the fewest splits
+    (fewer launches and a smaller dump for the same time)."""
+    fastest = min(ms for _, ms in timed)
+    close = [(t, ms) for t, ms in timed if ms <= fastest * (1 + TIE)]
+    return min(close, key=lambda r: (-r[0]["chunk_spectra"], r[0]["x_splits"], r[1]))
 
 
 def tune_batch_job(N: int, K: int, S: int, prec: str, log=print) -> Tuple[dict, float]:

@@ -91,6 +91,30 @@ def test_fstage_extreme_samples():
     assert np.max(np.abs(got - ref)) <= 1e-3
 
 
+@pytest.mark.parametrize("N,prec,tiles", [(5, "fp32", None), (20, "fp16", None), (2, "int8", None),
+                                           (33, "int16", None), (44, "fp32", dict(f_group=16)),
+                                           (5, "fp32", dict(f_group=16))])
+def test_padding_records_stay_zero(N, prec, tiles):
+    """Records of the padding antennas (N up to the 16-antenna block) hold
+    zeros after two integrations in the same buffer, whether the F-stage
+    stores them as zeros (padding sharing a 128-byte line with real antennas;
+    a float record may then hold -0.0) or never stores them (padding in lines
+    of its own)."""
+    K, S = 128, 40
+    print(f"\n[padding] N={N} {prec} tiles={tiles}", flush=True)
+    c = corr.Correlator(N, K, S, precision=prec, tiles=tiles)
+    for seed in (61, 62):
+        c.process(_packed(synth.recipe_plain(N=N, two_k=2 * K, seed=seed), S))
+        buf, n = c.debug_read_spectra()
+        c.read_cps()  # the integer forms need each integration read before the next
+    a_pad = corr.a_pad_of(N)
+    dt = {"fp32": np.float32, "fp16": np.float16, "int8": np.int8, "int16": np.int8}[prec]
+    rec = buf.view(dt).reshape(-1, K, corr.TQB, a_pad, 16 // np.dtype(dt).itemsize)
+    assert np.all(rec[:, :, :, N:] == 0)
+    assert np.any(rec[:, :, :, :N] != 0)
+    c.close()
+
+
 # ------------------------------------------------------------------ FP32 end to end
 
 @pytest.mark.parametrize("N,K,S", [(44, 256, 1024), (5, 128, 37), (20, 512, 100), (16, 1024, 24),

@@ -24,3 +24,16 @@ def test_table_lookup(tmp_path):
     assert tune.lookup(44, 256, 100, "fp32", path=str(p))["x_splits"] == 4
     assert tune.lookup(8, 128, 100, "int8", batch=True, path=str(p)) == {"x_splits": 2}
     assert tune.lookup(8, 128, 100, "int8", path=str(p)) is None
+
+
+def test_pick_prefers_simpler_tiling_within_tie():
+    a = {"chunk_spectra": 65536, "x_splits": 32, "f_group": 2}
+    b = {"chunk_spectra": 65536, "x_splits": 8, "f_group": 2}
+    c = {"chunk_spectra": 32768, "x_splits": 4, "f_group": 2}
+    # b is within 1% of the fastest (a) and has fewer splits; c is within 1%
+    # but takes two chunks
+    assert tune.pick([(a, 1.5770), (b, 1.5783), (c, 1.5790)])[0] is b
+    # outside the tie margin the fastest wins
+    assert tune.pick([(a, 1.50), (b, 1.60)])[0] is a
+    # among equal chunk and splits, the faster one
+    assert tune.pick([(b, 1.60), (dict(b, f_group=4), 1.59)])[1] == 1.59
