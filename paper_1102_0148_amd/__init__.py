@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libcorr.so")
 CORR_OK, CORR_EINVAL, CORR_ENOMEM, CORR_EHIP, CORR_ESTATE = 0, -1, -2, -3, -4
 CORR_FP32, CORR_FP16, CORR_INT8, CORR_INT16 = 0, 1, 2, 3
 CORR_CALIB_SPECTRA = 1024
+CORR_MAX_ANTENNAS, CORR_MAX_CHANNELS = 512, 1024
 PRECISIONS = {"fp32": CORR_FP32, "fp16": CORR_FP16, "int8": CORR_INT8, "int16": CORR_INT16}
 CORR_BATCH_BRANCHES, CORR_BATCH_PERSISTENT = 0, 1
 BATCH_MODES = {"branches": CORR_BATCH_BRANCHES, "persistent": CORR_BATCH_PERSISTENT}

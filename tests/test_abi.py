@@ -80,3 +80,13 @@ def test_record_layout_round_trip(prec, N, S):
     else:
         np.testing.assert_array_equal(rec[:n].astype(np.float32), spec[:n, 2, 3].real)
         np.testing.assert_array_equal(rec[tg:tg + n].astype(np.float32), spec[:n, 2, 3].imag)
+
+
+def test_binding_constants_match_header():
+    text = open(HEADER).read()
+    for name in ("CORR_MAX_ANTENNAS", "CORR_MAX_CHANNELS", "CORR_CALIB_SPECTRA", "CORR_FRAME_HEADER_BYTES"):
+        m = re.search(rf"#define {name} (\d+)", text)
+        if m and hasattr(corr, name):
+            assert getattr(corr, name) == int(m.group(1)), name
+    assert corr.CORR_MAX_ANTENNAS == int(re.search(r"#define CORR_MAX_ANTENNAS (\d+)", text).group(1))
+    assert corr.CORR_MAX_CHANNELS == int(re.search(r"#define CORR_MAX_CHANNELS (\d+)", text).group(1))

@@ -142,3 +142,45 @@ def test_batch_full_size_sampled_baselines():
             err = coef_error(v, oracle.cmac_f64(spec), len(ants))
             print(f"\n  job {j} N={N_} K={K_} int8 de-scaled: {err:.3g}", flush=True)
             assert err <= 3e-2
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "int8", "int16"])
+def test_maximum_shape_sampled_baselines(prec):
+    """The largest shape the library accepts: 512 antennas (eight 64-antenna
+    region rows), 1024 channels (a 2048-point FFT), and a ragged 45 spectra
+    (not a whole record in any form). Checked on baselines among antennas at
+    the region edges."""
+    N_, K_, S_ = corr.CORR_MAX_ANTENNAS, corr.CORR_MAX_CHANNELS, 45
+    ants = [0, 1, 63, 64, 255, 256, 447, 510, 511]
+    code = corr.PRECISIONS[prec]
+    recipe = synth.recipe_plain(N=N_, two_k=2 * K_, rho=0.05, seed=9) if prec in ("fp32", "fp16") else \
+        synth.recipe_tone(N=N_, two_k=2 * K_, seed=10, tone_bin=300, tone_amp=0.5)
+    print(f"\n[max shape] {prec} N={N_} K={K_} S={S_}", flush=True)
+    packed = synth.packed(recipe, 0, S_, device="cuda").contiguous()
+    c = corr.Correlator(N_, K_, S_, precision=prec)
+    c.process(packed)
+    rows = [oracle.baseline_index(N_, a, b) for i, a in enumerate(ants) for b in ants[i:]]
+    spec = oracle.spectra(packed[:, ants, :].cpu().numpy(), S_, len(ants), K_)
+    raw = c.read_cps_raw()[rows]
+    if prec in ("fp32", "fp16"):
+        err = coef_error(raw_to_complex(raw), oracle.cmac_f64(spec), len(ants))
+        print(f"  coefficient error {err:.3g}", flush=True)
+        assert err <= TOL[code]
+        return
+    buf, n = c.debug_read_spectra()
+    assert n == S_
+    if prec == "int8":
+        q = _sel_codes_n(buf, code, N_, K_, S_, ants)
+        exact = oracle.cmac_i64(q)
+    else:
+        tg = corr.record_times(code)
+        a_pad = corr.a_pad_of(N_)
+        ntq = ((S_ + tg - 1) // tg + corr.TQB - 1) // corr.TQB * corr.TQB
+        rec = np.asarray(buf)[: ntq * K_ * a_pad * 16].reshape(ntq // corr.TQB, K_, corr.TQB, a_pad, 16)
+        d = np.ascontiguousarray(rec[:, :, :, ants, :]).view(np.int8)
+        d = d.reshape(ntq // corr.TQB, K_, corr.TQB, len(ants), 2, 2, tg).astype(np.int32)
+        v = 255 * d[:, :, :, :, 0] + d[:, :, :, :, 1]
+        q = np.transpose(v, (0, 2, 5, 3, 1, 4)).reshape(ntq * tg, len(ants), K_, 2)[:S_].astype(np.int16)
+        exact = oracle.cmac_i64_16(q)
+    np.testing.assert_array_equal(raw, exact.astype(np.float64))
+    c.close()
