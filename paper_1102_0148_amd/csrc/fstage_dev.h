@@ -208,20 +208,23 @@ __device__ __forceinline__ uint4 make_record(const float *re, const float *im, f
         static_assert(TS == 4, "int16 record");
         // q = clamp(rint(x sc), -32512, 32512) as for int8, then the base-255
         // digits h = floor((q + 127.5) / 255), l = q - 255 h, both in
-        // [-127, 127] (q + 127.5 is a half-integer, never within 1/510 of a
-        // multiple of 255 after the division, and the product by the
-        // reciprocal is within 2^-16 of the quotient, so the floor is exact).
+        // [-127, 127].  For an integer q that h is also the integer nearest
+        // q / 255: q / 255 is never within 1/510 of a half-integer, and the
+        // product by the rounded reciprocal is within 2^-17 of the quotient,
+        // so adding 1.5 * 2^23 in the same fused operation rounds it to h
+        // exactly and leaves h in the low bits.
         // Record: [h of re x4][h of im x4][l of re x4][l of im x4].
+        constexpr float kMagic = 12582912.0f;
         uint32_t hb[8], lb[8];
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
             const float v = (t < 4 ? re[t] : im[t - 4]) * sc;
             wsat += (unsigned)__popcll(__ballot(fabsf(v) >= (float)kI16Max + 0.5f));
-            const float q = (__builtin_amdgcn_fmed3f(v, -(float)kI16Max, (float)kI16Max) + 12582912.0f) - 12582912.0f;
-            const float h = floorf((q + 127.5f) * (1.0f / 255.0f));
-            const float l = q - 255.0f * h;
-            hb[t] = __float_as_uint(h + 12582912.0f);
-            lb[t] = __float_as_uint(l + 12582912.0f);
+            const float q = (__builtin_amdgcn_fmed3f(v, -(float)kI16Max, (float)kI16Max) + kMagic) - kMagic;
+            const float hm = fmaf(q, 1.0f / 255.0f, kMagic);
+            const float l = fmaf(-255.0f, hm - kMagic, q);
+            hb[t] = __float_as_uint(hm);
+            lb[t] = __float_as_uint(l + kMagic);
         }
         uint32_t w[4];
 #pragma unroll

@@ -90,3 +90,4 @@ def test_binding_constants_match_header():
             assert getattr(corr, name) == int(m.group(1)), name
     assert corr.CORR_MAX_ANTENNAS == int(re.search(r"#define CORR_MAX_ANTENNAS (\d+)", text).group(1))
     assert corr.CORR_MAX_CHANNELS == int(re.search(r"#define CORR_MAX_CHANNELS (\d+)", text).group(1))
+
