@@ -184,3 +184,32 @@ def test_maximum_shape_sampled_baselines(prec):
         exact = oracle.cmac_i64_16(q)
     np.testing.assert_array_equal(raw, exact.astype(np.float64))
     c.close()
+
+
+@pytest.mark.parametrize("prec,chunk,splits", [("int8", 8192, 2), ("fp32", 2048, 1)])
+def test_cache_sized_chunks_full_integration(prec, chunk, splits):
+    """A whole 65536-spectrum integration processed in chunks whose records
+    fit the 256 MB Infinity Cache (int8: 8192 spectra, 201 MB; fp32: 2048
+    spectra, 201 MB), so the X-stage reads each chunk soon after the F-stage
+    wrote it: the same results as the whole-integration tiling."""
+    code = corr.PRECISIONS[prec]
+    recipe = synth.recipe_plain(N=N, two_k=2 * K, rho=0.05, seed=1) if prec == "fp32" else \
+        synth.recipe_tone(N=N, two_k=2 * K, seed=2, tone_bin=77, tone_amp=0.5)
+    print(f"\n[cache-sized chunks] {prec} chunk={chunk}", flush=True)
+    packed = synth.packed(recipe, 0, S, device="cuda").contiguous()
+    c = corr.Correlator(N, K, S, precision=prec, tiles=dict(chunk_spectra=chunk, x_splits=splits))
+    c.process(packed)
+    spec = oracle.spectra(packed[:, ANTS, :].cpu().numpy(), S, len(ANTS), K)
+    raw = c.read_cps_raw()
+    if prec == "fp32":
+        ref = oracle.cmac_f64(spec)
+        err = coef_error(_sub(raw_to_complex(raw), ref), ref, len(ANTS))
+        print(f"  coefficient error {err:.3g}", flush=True)
+        assert err <= TOL[code]
+        return
+    # the integer sums of the whole integration over the records of every
+    # chunk equal the whole-integration tiling's, bit for bit
+    w = corr.Correlator(N, K, S, precision=prec, tiles="auto")
+    w.process(packed)
+    np.testing.assert_array_equal(_sub(raw, None), _sub(w.read_cps_raw(), None))
+    np.testing.assert_array_equal(c.read_scales(), w.read_scales())
