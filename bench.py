@@ -212,6 +212,7 @@ def large_n(corr, torch, metrics, steps, warmup):
         out[prec] = {"antenna_msps": round(metrics.antenna_samples(N, two_k, S) / (ms * 1e-3) / 1e6, 1),
                      "ms_per_integration": round(ms, 4),
                      "x_tops": round(metrics.x_ops(N, Kc, S) / (x_ms * 1e-3) / 1e12, 2),
+                     "x_mfma": x_mfma(metrics, N, Kc, S, prec, x_ms),
                      "ms_f": round(st["ms_f"] / steps, 4), "ms_x": round(x_ms, 4), "tiles": c.tiles()}
         c.close()
         log(f"[bench] large N {prec}: {out[prec]}")
@@ -286,6 +287,18 @@ def batch(corr, torch, metrics, steps, warmup):
     return out
 
 
+def x_mfma(metrics, N, K, S, prec, x_ms):
+    """The X-stage's issued MFMA rate against the dense peak of its form
+    (issued operations from the block-pair count; rocprofv3's
+    SQ_INSTS_VALU_MFMA_MOPS counters give the same totals)."""
+    if x_ms <= 0:
+        return None
+    rate = metrics.x_mfma_ops(N, K, S, prec) / (x_ms * 1e-3) / 1e12
+    peak = metrics.MFMA_PEAK[prec]
+    return {"issued": round(rate, 2), "peak": peak, "unit": "TFLOP/s" if prec.startswith("fp") else "TOPS",
+            "frac": round(rate / peak, 4)}
+
+
 def cpu_baseline(inputs_cpu_sample, S_sample):
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -347,6 +360,7 @@ def main():
                                    "calib": round(stats["ms_calib"] / n_int, 4)},
             "launches_per_integration": {"f": stats["launches_f"] // n_int, "x": stats["launches_x"] // n_int},
             "tiles": tiles,
+            "x_mfma": x_mfma(metrics, N_ANT, K, S_INT, name, x_ms),
         }
         if name in ("int8", "int16"):
             forms[name]["saturated_fraction"] = stats["int8_saturated"] / max(

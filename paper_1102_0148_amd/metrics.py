@@ -30,6 +30,31 @@ def x_ops(N: int, K: int, S: int) -> float:
     return 8.0 * n_baselines(N) * K * S
 
 
+# MFMA operations the X-stage issues per entry of a 16 x 16 antenna block pair
+# per spectrum: fp32 forms three real products (re.re, im.im and
+# (re+im).(re+im)), two operations each; fp16 and int8 form two real products
+# over [re | im] operands of twice the length; int16 forms the int8 form's
+# products for four pairs of base-255 digits.
+MFMA_OPS_PER_ENTRY = {"fp32": 6, "fp16": 8, "int8": 8, "int16": 32}
+# Dense MFMA peaks of MI355X per form (int16 runs on the int8 MFMA), in
+# TFLOP/s or TOPS.
+MFMA_PEAK = {"fp32": 157.3, "fp16": 2500.0, "int8": 5000.0, "int16": 5000.0}
+
+
+def padded_antennas(N: int) -> int:
+    """Antennas the X-stage computes over: whole 16-antenna blocks up to 96
+    antennas, whole 64-antenna region rows beyond."""
+    return 16 * ((N + 15) // 16) if N <= 96 else (N + 63) // 64 * 64
+
+
+def x_mfma_ops(N: int, K: int, S: int, prec: str) -> float:
+    """Operations the X-stage's MFMA instructions issue for S spectra: the
+    regions tile the triangle of block pairs of the padded antennas, so every
+    block pair is computed once (diagonal blocks in full)."""
+    nblk = padded_antennas(N) // 16
+    return float(MFMA_OPS_PER_ENTRY[prec]) * 256 * (nblk * (nblk + 1) // 2) * K * S
+
+
 def antenna_samples(N: int, two_k: int, S: int) -> float:
     return float(N) * two_k * S
 

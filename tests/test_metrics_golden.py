@@ -31,3 +31,19 @@ def test_abstract_rate_in_antenna_samples():
     # 4-bit samples: 2 antenna-samples per byte
     assert mb * 2 == 1470
     assert metrics.antenna_msps(44, 512, 1, 1.0) == 44 * 512 / 1e6
+
+
+def test_x_mfma_ops_block_pairs():
+    """N = 44 pads to 3 blocks of 16: 6 block pairs of 256 entries. The
+    totals match the per-dispatch MFMA counters of the committed profile
+    (fp32 1.55e11, int8 2.06e11, int16 8.25e11 per 65536-spectrum
+    integration)."""
+    from paper_1102_0148_amd import metrics
+    assert metrics.padded_antennas(44) == 48
+    assert metrics.padded_antennas(256) == 256 and metrics.padded_antennas(100) == 128
+    base = 256 * 6 * 256 * 65536
+    assert metrics.x_mfma_ops(44, 256, 65536, "fp32") == 6 * base
+    assert metrics.x_mfma_ops(44, 256, 65536, "int8") == 8 * base
+    assert metrics.x_mfma_ops(44, 256, 65536, "int16") == 32 * base
+    assert abs(metrics.x_mfma_ops(44, 256, 65536, "fp32") - 1.5466e11) / 1.5466e11 < 1e-3
+    assert abs(metrics.x_mfma_ops(44, 256, 65536, "int16") - 8.246e11) / 8.246e11 < 1e-3
