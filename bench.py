@@ -299,16 +299,30 @@ def x_mfma(metrics, N, K, S, prec, x_ms):
             "frac": round(rate / peak, 4)}
 
 
-def cpu_baseline(inputs_cpu_sample, S_sample):
+def cpu_baseline(inputs_cpu_sample, S_sample, S_one_thread):
+    """The oracle timed on the host's cores, then on one thread over a smaller
+    sample (the analogue of the paper's multicore-against-one-thread figure)."""
     import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = oracle.get_threads()
     t0 = time.perf_counter()
     oracle.correlate(inputs_cpu_sample, S_sample, N_ANT, K)
     dt = time.perf_counter() - t0
     rate = N_ANT * S_sample * TWO_K / dt / 1e6
-    return {"value": round(rate, 3), "unit": "antenna-MS/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {S_sample} spectra of integration 1 (N={N_ANT}, 2K={TWO_K}), "
-                      f"float64 FFT + pairwise CMAC, {dt:.1f} s"}
+    out = {"value": round(rate, 3), "unit": "antenna-MS/s", "cores": threads, "kind": "oracle",
+           "sample": f"first {S_sample} spectra of integration 1 (N={N_ANT}, 2K={TWO_K}), "
+                     f"float64 FFT + pairwise CMAC, {dt:.1f} s"}
+    if S_one_thread > 0:
+        oracle.set_threads(1)
+        try:
+            t0 = time.perf_counter()
+            oracle.correlate(inputs_cpu_sample[:S_one_thread], S_one_thread, N_ANT, K)
+            dt1 = time.perf_counter() - t0
+        finally:
+            oracle.set_threads(threads)
+        rate1 = N_ANT * S_one_thread * TWO_K / dt1 / 1e6
+        out["one_thread"] = {"value": round(rate1, 3), "sample": f"first {S_one_thread} spectra, {dt1:.1f} s",
+                             "multicore_speedup": round(rate / rate1, 1)}
+    return out
 
 
 def main():
@@ -318,6 +332,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-spectra", type=int, default=65536)
+    ap.add_argument("--cpu-spectra-one-thread", type=int, default=4096)
     ap.add_argument("--forms", default="fp32,fp16,int8,int16")
     ap.add_argument("--no-extra", action="store_true", help="skip the large-N and batch workloads")
     ap.add_argument("--copy-probe", action="store_true",
@@ -432,7 +447,7 @@ def main():
         import synth
         recipe = synth.recipe_plain(N=N_ANT, two_k=TWO_K, rho=0.05, seed=1)
         sample = synth.packed(recipe, 0, args.cpu_spectra, device="cuda").cpu().numpy()
-        out["cpu_baseline"] = cpu_baseline(sample, args.cpu_spectra)
+        out["cpu_baseline"] = cpu_baseline(sample, args.cpu_spectra, min(args.cpu_spectra_one_thread, args.cpu_spectra))
     print(json.dumps(out))
 
 

@@ -60,6 +60,8 @@ def _load():
         "orc_scales_n": (i32, [P, i32, i32, i32, i32, i32, ctypes.c_double, P]),
         "orc_quantise16": (i32, [P, i32, i32, i32, P, P]),
         "orc_cmac_i64_16": (i32, [P, i32, i32, i32, i32, P]),
+        "orc_set_threads": (i32, [i32]),
+        "orc_get_threads": (i32, []),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -246,3 +248,12 @@ def track(spec: np.ndarray, delay=None, delay_rate=None, phase=None, phase_rate=
 def correlate(packed: np.ndarray, S: int, N: int, K: int) -> np.ndarray:
     """Whole float64 path: packed [S][N][K] -> visibilities complex128 [nb][K]."""
     return cmac_f64(spectra(packed, S, N, K))
+
+
+def set_threads(n: int) -> None:
+    """Number of OpenMP threads the oracle's loops use (timing only)."""
+    _check(_load().orc_set_threads(int(n)), "orc_set_threads")
+
+
+def get_threads() -> int:
+    return int(_load().orc_get_threads())

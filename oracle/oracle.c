@@ -56,6 +56,7 @@
  * the code implements the rule as stated.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -467,4 +468,21 @@ int orc_vis_single(const uint8_t *packed, int S, int N, int K, int a, int b, int
     out[1] = vi;
     free(wr); free(wi);
     return ORC_OK;
+}
+
+/* Threads the OpenMP loops above use (a timing control).  Every parallel
+ * loop but one writes disjoint outputs in a fixed order of summation, so its
+ * result does not depend on the count; orc_vis_single's reduction over
+ * spectra regroups its float64 sum by thread, which moves it by rounding
+ * only.  */
+int orc_set_threads(int n)
+{
+    if (n < 1) return ORC_EINVAL;
+    omp_set_num_threads(n);
+    return ORC_OK;
+}
+
+int orc_get_threads(void)
+{
+    return omp_get_max_threads();
 }
