@@ -484,3 +484,20 @@ def test_scales16_are_256_times_int8_scales(orc):
     rng = np.random.default_rng(12)
     spec = rng.standard_normal((30, 3, 16)) * 40 + 1j * rng.standard_normal((30, 3, 16)) * 40
     np.testing.assert_array_equal(orc.scales_n(spec, 20, 20, 32512.0), 256 * orc.scales(spec, 20))
+
+
+def test_thread_count_leaves_results_unchanged(orc):
+    """The thread-count control only times: spectra and visibilities are the
+    same, bit for bit, on one thread and on all of them."""
+    packed = synth.packed(synth.recipe_plain(N=6, two_k=64, seed=21), 0, 40).numpy()
+    n = orc.get_threads()
+    full = orc.correlate(packed, 40, 6, 32)
+    orc.set_threads(1)
+    try:
+        assert orc.get_threads() == 1
+        one = orc.correlate(packed, 40, 6, 32)
+    finally:
+        orc.set_threads(n)
+    np.testing.assert_array_equal(full, one)
+    with pytest.raises(ValueError):
+        orc.set_threads(0)
