@@ -177,13 +177,13 @@ int corr_set_tracking(corr_handle h, const double *delay, const double *delay_ra
 /* Read the integration buffer and clear it.  Waits for `the last stream`
  * used with this handle.  out: HOST pointer to nb*K*2 floats, nb =
  * N(N+1)/2, layout [baseline][channel][re, im], in the units of the
- * unnormalised transform (INT8 values are divided by s_a*s_b, the two
- * antennas' scales).  CORR_ESTATE if nothing was processed since the last
+ * unnormalised transform (INT8 and INT16 values are divided by s_a*s_b,
+ * the two antennas' scales).  CORR_ESTATE if nothing was processed since the last
  * read.  */
 int corr_read_cps(corr_handle h, float *out);
 
-/* As corr_read_cps but the float64 buffer as it is: for INT8 the exact
- * integer sums in quantised units.  out: HOST pointer to nb*K*2 doubles.  */
+/* As corr_read_cps but the float64 buffer as it is: for INT8 and INT16 the
+ * exact integer sums in quantised units.  out: HOST pointer to nb*K*2 doubles.  */
 int corr_read_cps_raw(corr_handle h, double *out);
 
 /* Asynchronous read: enqueue on `stream` a copy of the raw float64 buffer
@@ -191,8 +191,9 @@ int corr_read_cps_raw(corr_handle h, double *out);
  * memory -- then clear the buffer.  Does not wait.  */
 int corr_read_cps_async(corr_handle h, double *dst, void *stream);
 
-/* INT8 only: the scales [N][K] (float) used by the last integration.
- * out: HOST pointer.  Waits for the handle's stream.  */
+/* INT8 and INT16 only: the scales [N][K] (float) used by the last
+ * integration.  out: HOST pointer.  Waits for the handle's stream.
+ * CORR_ESTATE for the float forms or before the first integration.  */
 int corr_read_scales(corr_handle h, float *out);
 
 /* Bytes of spectra in the library layout for n_spectra spectra (the size of
@@ -202,13 +203,16 @@ int corr_read_scales(corr_handle h, float *out);
  * rounded up to 16 (to 64 above 96 antennas), tq padded to a multiple of 16;
  * a record holds TG consecutive spectra of one antenna and channel as
  * [re x TG][im x TG] in the precision's type (float, TG=2; half, TG=4; int8,
- * TG=8).  Records of padding antennas, and of spectra from n_spectra up to
- * the next multiple of 4*TG, must be zero.  */
+ * TG=8).  INT16 (TG=4) stores each code q as base-255 digits q = 255 h + l,
+ * h and l int8 in [-127, 127]: [h of re x4][h of im x4][l of re x4][l of im
+ * x4].  Records of padding antennas, and of spectra from n_spectra up to the
+ * next multiple of 4*TG (8*TG for INT16), must be zero.  */
 size_t corr_spectra_bytes(corr_handle h, int n_spectra);
 
 /* X-stage + dump only, on n_spectra spectra already in the library layout
  * (DEVICE pointer, corr_spectra_bytes(h, n_spectra) bytes).  Adds into the
- * integration buffer like corr_process; INT8 spectra are taken as given.  */
+ * integration buffer like corr_process; INT8 and INT16 spectra are taken as
+ * given (no calibration).  */
 int corr_process_spectra(corr_handle h, const void *spectra, int n_spectra, void *stream);
 
 /* Copy the spectra of the last chunk the F-stage produced (library layout)
