@@ -37,3 +37,4 @@ def test_pick_prefers_simpler_tiling_within_tie():
     assert tune.pick([(a, 1.50), (b, 1.60)])[0] is a
     # among equal chunk and splits, the faster one
     assert tune.pick([(b, 1.60), (dict(b, f_group=4), 1.59)])[1] == 1.59
+
