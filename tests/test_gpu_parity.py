@@ -393,3 +393,44 @@ def test_every_autotuner_candidate_passes_parity(prec):
                 np.testing.assert_array_equal(raw, first)
         else:
             assert coef_error(raw_to_complex(raw), ref, N) <= TOL[corr.PRECISIONS[prec]], t
+
+
+# ------------------------------------------------------------------ degenerate cases
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "int8", "int16"])
+def test_single_spectrum_two_antennas(prec):
+    """The smallest job: two antennas, 128 channels, one spectrum (one
+    partial record, padded by zero spectra), in every form."""
+    N, K, S = 2, 128, 1
+    print(f"\n[degenerate] {prec} N={N} K={K} S={S}", flush=True)
+    packed = _packed(synth.recipe_plain(N=N, two_k=2 * K, seed=71), S)
+    c = corr.Correlator(N, K, S, precision=prec)
+    c.process(packed)
+    buf, n = c.debug_read_spectra()
+    assert n == S
+    raw = c.read_cps_raw()
+    assert raw.shape == (3, K, 2)
+    spec = oracle.spectra(packed.cpu().numpy(), S, N, K)
+    code = corr.PRECISIONS[prec]
+    if prec in ("fp32", "fp16"):
+        assert coef_error(raw_to_complex(raw), oracle.cmac_f64(spec), N) <= TOL[code]
+    else:
+        q = corr.records_to_spectra(buf, code, N, K, S)
+        exact = oracle.cmac_i64(q) if prec == "int8" else oracle.cmac_i64_16(q)
+        np.testing.assert_array_equal(raw, exact.astype(np.float64))
+    c.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "int8", "int16"])
+def test_all_zero_input(prec):
+    """Silent antennas: every visibility is zero, and the integer forms give
+    every zero-power channel the scale 1 (no division by zero)."""
+    N, K, S = 5, 128, 40
+    packed = torch.zeros(S * N * K, dtype=torch.uint8, device="cuda")
+    c = corr.Correlator(N, K, S, precision=prec)
+    c.process(packed)
+    if prec in ("int8", "int16"):
+        np.testing.assert_array_equal(c.read_scales(), np.ones((N, K), dtype=np.float32))
+    raw = c.read_cps_raw()
+    assert np.all(raw == 0)
+    c.close()
