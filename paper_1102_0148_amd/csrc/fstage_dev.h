@@ -212,7 +212,11 @@ __device__ __forceinline__ uint4 make_record(const float *re, const float *im, f
         // q / 255: q / 255 is never within 1/510 of a half-integer, and the
         // product by the rounded reciprocal is within 2^-17 of the quotient,
         // so adding 1.5 * 2^23 in the same fused operation rounds it to h
-        // exactly and leaves h in the low bits.
+        // exactly and leaves h in the low bits.  The bits of 1.5 * 2^23 + x
+        // are those of 1.5 * 2^23 plus x (an integer below 2^22), whose low
+        // byte is zero; the low byte of the sum of the bits of q's and h's
+        // biased floats is therefore (q + h) mod 256, which is
+        // (q - 255 h) mod 256 = l mod 256, the byte the record holds.
         // Record: [h of re x4][h of im x4][l of re x4][l of im x4].
         constexpr float kMagic = 12582912.0f;
         uint32_t hb[8], lb[8];
@@ -220,11 +224,10 @@ __device__ __forceinline__ uint4 make_record(const float *re, const float *im, f
         for (int t = 0; t < 8; ++t) {
             const float v = (t < 4 ? re[t] : im[t - 4]) * sc;
             wsat += (unsigned)__popcll(__ballot(fabsf(v) >= (float)kI16Max + 0.5f));
-            const float q = (__builtin_amdgcn_fmed3f(v, -(float)kI16Max, (float)kI16Max) + kMagic) - kMagic;
-            const float hm = fmaf(q, 1.0f / 255.0f, kMagic);
-            const float l = fmaf(-255.0f, hm - kMagic, q);
+            const float qm = __builtin_amdgcn_fmed3f(v, -(float)kI16Max, (float)kI16Max) + kMagic;
+            const float hm = fmaf(qm - kMagic, 1.0f / 255.0f, kMagic);
             hb[t] = __float_as_uint(hm);
-            lb[t] = __float_as_uint(l + kMagic);
+            lb[t] = __float_as_uint(qm) + __float_as_uint(hm);
         }
         uint32_t w[4];
 #pragma unroll

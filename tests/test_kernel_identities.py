@@ -24,3 +24,23 @@ def test_int16_digit_rule_by_nearest_integer():
     hh, ll = corr.int16_digits(q.astype(np.int64))
     np.testing.assert_array_equal(hh, h)
     np.testing.assert_array_equal(ll, l)
+
+
+def test_int16_low_digit_byte_from_biased_bits():
+    """The F-stage writes the low digit's byte as the low byte of the sum of
+    the bit patterns of 1.5 * 2^23 + q and 1.5 * 2^23 + h (both exact
+    floats): for every code that byte is l = q - 255 h as a two's-complement
+    int8."""
+    q = np.arange(-32512, 32513, dtype=np.int64)
+    h = np.floor((q + 127.5) / 255.0).astype(np.int64)
+    l = q - 255 * h
+    magic = np.float32(12582912.0)
+    qm = (magic + q.astype(np.float32)).view(np.uint32).astype(np.int64)
+    hm = (magic + h.astype(np.float32)).view(np.uint32).astype(np.int64)
+    bias = int(np.float32(magic).view(np.uint32))
+    np.testing.assert_array_equal(qm - bias, q)
+    np.testing.assert_array_equal(hm - bias, h)
+    assert bias & 0xFF == 0
+    byte = ((qm + hm) & 0xFF).astype(np.uint8).view(np.int8)
+    np.testing.assert_array_equal(byte, l.astype(np.int8))
+
