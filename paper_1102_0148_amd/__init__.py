@@ -492,9 +492,10 @@ class Batch:
             names = {v: k for k, v in PRECISIONS.items()}
             tiles = {}
             for j, (N, K, S, p) in enumerate(self.jobs):
-                # the persistent kernel has its own table entries; branches
-                # run the single-job kernels
-                found = tune.lookup(N, K, S, names[p], batch=self.mode == CORR_BATCH_PERSISTENT)
+                # each batch mode has its own table entries (a job's chunk
+                # and F group are fixed in a batch; only x_splits is tuned)
+                found = tune.lookup(N, K, S, names[p],
+                                    batch="persistent" if self.mode == CORR_BATCH_PERSISTENT else "branches")
                 if found:
                     tiles[j] = {"x_splits": found["x_splits"]}
         try:

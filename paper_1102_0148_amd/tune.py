@@ -3,12 +3,11 @@
 For one job shape (N antennas, K channels, n_spectra, precision) it times
 every candidate (chunk_spectra, x_splits, f_group) with the library's own
 stage timers (HIP events on the launch stream) over a few integrations of
-synthetic input, and keeps the fastest.  Jobs of the persistent batch kernel
-(one chunk per job, the F-stage group fixed by that kernel) are tuned over
-x_splits in a persistent batch of their own.  Results go to a JSON table keyed
-by (arch, N, K, n_spectra, precision[, batch]) that Correlator(tiles="auto")
-and Batch(tiles="auto") read; a branches-mode batch runs the single-job
-kernels and reads the single-job entries.
+synthetic input, and keeps the fastest.  Batch jobs (one chunk per job, the
+F-stage group fixed) are tuned over x_splits in a batch of their own, once
+per batch mode.  Results go to a JSON
+table keyed by (arch, N, K, n_spectra, precision[, batch mode]) that
+Correlator(tiles="auto") and Batch(tiles="auto") read.
 
 Run on the GPU:  python -m paper_1102_0148_amd.tune --out tuned.json [shapes]
 """
@@ -43,8 +42,12 @@ def f_lds_bytes(K: int, prec: str, group: int) -> int:
     return record_times(prec) * group * slot * 8 + fpr * K
 
 
-def key(N: int, K: int, S: int, prec: str, batch: bool = False) -> str:
-    return f"{ARCH}:N={N}:K={K}:S={S}:{prec}" + (":batch" if batch else "")
+def key(N: int, K: int, S: int, prec: str, batch=False) -> str:
+    """Table key; batch is False (a single job), True or "persistent" (a job
+    of the persistent batch kernel) or "branches" (a job on a branch of a
+    batch graph, whose chunk and F group are fixed)."""
+    suffix = "" if not batch else (":branches" if batch == "branches" else ":batch")
+    return f"{ARCH}:N={N}:K={K}:S={S}:{prec}" + suffix
 
 
 def candidates(N: int, K: int, S: int, prec: str) -> List[dict]:
@@ -70,7 +73,7 @@ def load_table(path: str = TABLE) -> Dict[str, dict]:
     return {}
 
 
-def lookup(N: int, K: int, S: int, prec: str, batch: bool = False, path: str = TABLE) -> Optional[dict]:
+def lookup(N: int, K: int, S: int, prec: str, batch=False, path: str = TABLE) -> Optional[dict]:
     return load_table(path).get(key(N, K, S, prec, batch))
 
 
@@ -156,7 +159,9 @@ def pick(timed: List[Tuple[dict, float]]) -> Tuple[dict, float]:
     return min(close, key=lambda r: (-r[0]["chunk_spectra"], r[0]["x_splits"], r[1]))
 
 
-def tune_batch_job(N: int, K: int, S: int, prec: str, log=print) -> Tuple[dict, float]:
+def tune_batch_job(N: int, K: int, S: int, prec: str, mode: str = "persistent", log=print) -> Tuple[dict, float]:
+    """x_splits of one batch job (its chunk and F group are fixed in a
+    batch), timed in a batch of its own in the given mode."""
     import torch
     import paper_1102_0148_amd as corr
     import synth
@@ -165,7 +170,7 @@ def tune_batch_job(N: int, K: int, S: int, prec: str, log=print) -> Tuple[dict, 
     for s in SPLITS:
         if PARTIAL_LIMIT[prec] and S / s > PARTIAL_LIMIT[prec]:
             continue
-        b = corr.Batch([(N, K, S, prec)], tiles={0: {"x_splits": s}}, mode="persistent")
+        b = corr.Batch([(N, K, S, prec)], tiles={0: {"x_splits": s}}, mode=mode)
         try:
             b.process([x])
             b.read_cps_raw(0)
@@ -180,7 +185,7 @@ def tune_batch_job(N: int, K: int, S: int, prec: str, log=print) -> Tuple[dict, 
             ms = e0.elapsed_time(e1) / 3
         finally:
             b.close()
-        log(f"  batch {prec} N={N} K={K} x_splits={s} {ms:.4f} ms")
+        log(f"  batch {mode} {prec} N={N} K={K} x_splits={s} {ms:.4f} ms")
         if best is None or ms < best[1]:
             best = ({"x_splits": s}, ms)
     return best
@@ -194,6 +199,7 @@ def main(argv: Optional[Iterable[str]] = None):
     ap.add_argument("--batch", default="8:128:16384,12:256:16384,16:512:16384,24:256:16384,"
                                        "32:1024:16384,44:256:16384,64:512:16384,96:256:16384")
     ap.add_argument("--batch-precisions", default="int8,fp32")
+    ap.add_argument("--batch-modes", default="persistent,branches")
     args = ap.parse_args(argv)
     sys.path.insert(0, os.path.dirname(HERE))
     import torch
@@ -210,9 +216,11 @@ def main(argv: Optional[Iterable[str]] = None):
     for item in filter(None, args.batch.split(",")):
         N, K, S = (int(v) for v in item.split(":"))
         for prec in args.batch_precisions.split(","):
-            best, ms = tune_batch_job(N, K, S, prec)
-            table[key(N, K, S, prec, batch=True)] = dict(best, ms=round(ms, 4))
-            print(f"best {key(N, K, S, prec, True)}: {table[key(N, K, S, prec, True)]}", flush=True)
+            for mode in args.batch_modes.split(","):
+                best, ms = tune_batch_job(N, K, S, prec, mode)
+                k = key(N, K, S, prec, batch=mode)
+                table[k] = dict(best, ms=round(ms, 4))
+                print(f"best {k}: {table[k]}", flush=True)
             with open(args.out, "w") as f:
                 json.dump(table, f, indent=1, sort_keys=True)
 

@@ -38,3 +38,10 @@ def test_pick_prefers_simpler_tiling_within_tie():
     # among equal chunk and splits, the faster one
     assert tune.pick([(b, 1.60), (dict(b, f_group=4), 1.59)])[1] == 1.59
 
+
+def test_keys_per_batch_mode():
+    assert tune.key(8, 128, 100, "int8") == "gfx950:N=8:K=128:S=100:int8"
+    assert tune.key(8, 128, 100, "int8", batch=True) == "gfx950:N=8:K=128:S=100:int8:batch"
+    assert tune.key(8, 128, 100, "int8", batch="persistent") == "gfx950:N=8:K=128:S=100:int8:batch"
+    assert tune.key(8, 128, 100, "int8", batch="branches") == "gfx950:N=8:K=128:S=100:int8:branches"
+
