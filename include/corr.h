@@ -265,9 +265,13 @@ typedef struct {
  * Tile choices come from the autotuner's table (corr_batch_set_tiles), else
  * defaults.  NULL on error.  */
 corr_handle corr_batch_create(const corr_job *jobs, int n_jobs);
-/* Tiles of one job: chunk_spectra must be 0 or the whole job rounded up to
- * 64 (a batch job is one chunk), f_group 0 or the default for its K and
- * precision; x_splits is free.  Before the first corr_batch_process only. */
+/* Tiles of one job, checked as by corr_set_tiles.  In CORR_BATCH_BRANCHES
+ * mode a job runs its tiles as a single correlator would.  The persistent
+ * kernel runs every job as one chunk with the F group it is compiled for, so
+ * in CORR_BATCH_PERSISTENT mode chunk_spectra must be 0 or the whole job
+ * rounded up to 64 and f_group 0 or the default for the job's K and
+ * precision; otherwise the first corr_batch_process fails with CORR_EINVAL.
+ * Before the first corr_batch_process only. */
 int corr_batch_set_tiles(corr_handle b, int job, const corr_tiles *t);
 /* mode: CORR_BATCH_BRANCHES or CORR_BATCH_PERSISTENT.  Before the first
  * corr_batch_process only (CORR_ESTATE after), CORR_EINVAL for another

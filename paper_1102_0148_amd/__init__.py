@@ -480,7 +480,7 @@ class Batch:
     graph: each job's own kernels on parallel branches ("branches", the
     default) or one persistent kernel over every job ("persistent").
     jobs: list of (N, K, n_spectra, precision); tiles: "auto" (the
-    autotuner's table) or {job index: {"x_splits": s}}."""
+    autotuner's table) or {job index: corr_tiles fields}."""
 
     def __init__(self, jobs, tiles=None, mode="branches"):
         self.jobs = [(int(N), int(K), int(S), PRECISIONS[p] if isinstance(p, str) else int(p))
@@ -492,12 +492,17 @@ class Batch:
             names = {v: k for k, v in PRECISIONS.items()}
             tiles = {}
             for j, (N, K, S, p) in enumerate(self.jobs):
-                # each batch mode has its own table entries (a job's chunk
-                # and F group are fixed in a batch; only x_splits is tuned)
-                found = tune.lookup(N, K, S, names[p],
-                                    batch="persistent" if self.mode == CORR_BATCH_PERSISTENT else "branches")
-                if found:
-                    tiles[j] = {"x_splits": found["x_splits"]}
+                # a branch runs the single-job kernels with the single-job
+                # entry; the persistent kernel has entries of its own (one
+                # chunk and its F group per job, x_splits tuned)
+                if self.mode == CORR_BATCH_PERSISTENT:
+                    found = tune.lookup(N, K, S, names[p], batch="persistent")
+                    if found:
+                        tiles[j] = {"x_splits": found["x_splits"]}
+                else:
+                    found = tune.lookup(N, K, S, names[p])
+                    if found:
+                        tiles[j] = {k: found[k] for k in ("chunk_spectra", "x_splits", "f_group")}
         try:
             corr_batch_set_mode(self.h, self.mode)
             for j, t in (tiles or {}).items():

@@ -22,13 +22,15 @@ template <int M, int PREC, int GA, bool POWER>
 __global__ __launch_bounds__(kThreads) void fstage_kernel(FArgs kargs) {
     using Sh = FShape<M, PREC, GA, POWER>;
     // a replayed graph passes the input through a device slot that the host
-    // rewrites before each replay.  The cast through the global address space
-    // keeps the input loads global: from a generic pointer they would be flat
-    // loads, which also count against lgkmcnt, so every wait for LDS would
-    // wait for the next tile's prefetch too.
+    // rewrites before each replay; a chunk starts s_base spectra into it.
+    // The cast through the global address space keeps the input loads
+    // global: from a generic pointer they would be flat loads, which also
+    // count against lgkmcnt, so every wait for LDS would wait for the next
+    // tile's prefetch too.
     typedef const __attribute__((address_space(1))) uint8_t *gptr;
     FArgs args = kargs;
-    if (args.in_slot) args.in = (const uint8_t *)*reinterpret_cast<const gptr *>(args.in_slot);
+    if (args.in_slot)
+        args.in = (const uint8_t *)*reinterpret_cast<const gptr *>(args.in_slot) + (int64_t)args.s_base * args.N * M;
     static_assert(Sh::LDS <= 160 * 1024, "LDS budget");
     __shared__ float2 zbuf[Sh::NF * Sh::SLOT];
     __shared__ __attribute__((aligned(16))) uint32_t bbuf[Sh::FPR * (M / 4)];

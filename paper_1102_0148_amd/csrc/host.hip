@@ -396,7 +396,6 @@ int process_one(corr_ctx *h, const uint8_t *in, hipStream_t st) {
     const int ga = h->tiles.f_group;
     const int ngroups = (h->N + ga - 1) / ga;
     const int64_t frame = (int64_t)h->N * h->K;
-    if (h->in_slot && chunk < h->S) return fail(CORR_EINVAL, "a job read through an input slot is one chunk");
     if (h->track_on && h->track_dirty) {
         // pageable source: the copy is staged before this call returns
         HIP_TRY(hipMemcpyAsync(h->track, h->track_host.data(), h->track_host.size() * sizeof(double4),
@@ -409,6 +408,7 @@ int process_one(corr_ctx *h, const uint8_t *in, hipStream_t st) {
         // whole k-blocks; int16 steps take two k-blocks
         const int ntq_used = round_up((Sc + h->TG - 1) / h->TG, h->prec == kINT16 ? 8 : 4);
         FArgs fa{};
+        // through a slot, the kernel adds the chunk's offset (s_base) itself
         fa.in = h->in_slot ? nullptr : in + (int64_t)c0 * frame;
         fa.in_slot = h->in_slot;
         fa.track = h->track_on ? h->track : nullptr;
@@ -874,14 +874,11 @@ int corr_batch_set_tiles(corr_handle b, int job, const corr_tiles *t) {
     if (job < 0 || job >= (int)b->jobs.size()) return fail(CORR_EINVAL, "job %d out of range", job);
     if (b->gexec) return fail(CORR_ESTATE, "tiles are fixed once the batch has run");
     corr_ctx *h = b->jobs[job];
-    const int whole = round_up(h->S, 64);
-    if (t->chunk_spectra != 0 && t->chunk_spectra != whole)
-        return fail(CORR_EINVAL, "a batch job is one chunk: chunk_spectra must be 0 or %d", whole);
-    const int g = batch_default_group(h->K, h->prec);
-    if (t->f_group != 0 && t->f_group != g)
-        return fail(CORR_EINVAL, "a batch job uses f_group %d for K=%d in this precision", g, h->K);
-    if (t->x_splits < 0 || t->x_splits > 64) return fail(CORR_EINVAL, "x_splits=%d out of [0, 64]", t->x_splits);
-    h->tiles.x_splits = t->x_splits;
+    // the same checks as for a single correlator; the persistent mode's own
+    // constraints (one chunk, its F group) are checked when it is built
+    const int rc = check_tiles(h, t);
+    if (rc) return rc;
+    h->tiles = *t;
     return CORR_OK;
 }
 
@@ -913,8 +910,7 @@ int batch_build_branches(corr_ctx *b) {
     std::vector<double> work(nj);
     for (int j = 0; j < nj; ++j) {
         corr_ctx *h = b->jobs[j];
-        h->tiles.chunk_spectra = round_up(h->S, 64);
-        h->tiles.f_group = batch_default_group(h->K, h->prec);
+        // the job's own tiles, as a single correlator would run them
         int rc = plan(h);
         if (rc) return rc;
         h->in_slot = b->in_ptrs + j;
@@ -970,8 +966,16 @@ int batch_build(corr_ctx *b) {
     int lds = 0;
     for (int j = 0; j < nj; ++j) {
         corr_ctx *h = b->jobs[j];
-        h->tiles.chunk_spectra = round_up(h->S, 64);
-        h->tiles.f_group = batch_default_group(h->K, h->prec);
+        // the persistent kernel runs each job as one chunk with the F group
+        // it is compiled for
+        const int whole = round_up(h->S, 64), g = batch_default_group(h->K, h->prec);
+        if ((h->tiles.chunk_spectra != 0 && h->tiles.chunk_spectra != whole) ||
+            (h->tiles.f_group != 0 && h->tiles.f_group != g))
+            return fail(CORR_EINVAL,
+                        "job %d: the persistent batch kernel needs chunk_spectra 0 or %d and f_group 0 or %d", j,
+                        whole, g);
+        h->tiles.chunk_spectra = whole;
+        h->tiles.f_group = g;
         int rc = plan(h);
         if (rc) return rc;
         // regions small enough for the batch kernel's register budget
@@ -1139,7 +1143,7 @@ int corr_batch_process(corr_handle b, const void *const *packed, void *stream) {
         h->started = true;
         h->last_stream = st;
         h->accumulated += h->S;
-        h->last_chunk = h->S;
+        h->last_chunk = h->S - (h->S - 1) / h->tiles.chunk_spectra * h->tiles.chunk_spectra;
     }
     return CORR_OK;
 }

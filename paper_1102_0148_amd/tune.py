@@ -3,11 +3,12 @@
 For one job shape (N antennas, K channels, n_spectra, precision) it times
 every candidate (chunk_spectra, x_splits, f_group) with the library's own
 stage timers (HIP events on the launch stream) over a few integrations of
-synthetic input, and keeps the fastest.  Batch jobs (one chunk per job, the
-F-stage group fixed) are tuned over x_splits in a batch of their own, once
-per batch mode.  Results go to a JSON
-table keyed by (arch, N, K, n_spectra, precision[, batch mode]) that
-Correlator(tiles="auto") and Batch(tiles="auto") read.
+synthetic input, and keeps the fastest.  Jobs of the persistent batch kernel
+(one chunk per job, the F-stage group fixed) are tuned over x_splits in a
+batch of their own; a branch of a batch graph runs the single-job kernels and
+takes the single-job entries.  Results go to a JSON table keyed by (arch, N,
+K, n_spectra, precision[, batch mode]) that Correlator(tiles="auto") and
+Batch(tiles="auto") read.
 
 Run on the GPU:  python -m paper_1102_0148_amd.tune --out tuned.json [shapes]
 """
@@ -199,7 +200,7 @@ def main(argv: Optional[Iterable[str]] = None):
     ap.add_argument("--batch", default="8:128:16384,12:256:16384,16:512:16384,24:256:16384,"
                                        "32:1024:16384,44:256:16384,64:512:16384,96:256:16384")
     ap.add_argument("--batch-precisions", default="int8,fp32")
-    ap.add_argument("--batch-modes", default="persistent,branches")
+    ap.add_argument("--batch-modes", default="persistent")
     args = ap.parse_args(argv)
     sys.path.insert(0, os.path.dirname(HERE))
     import torch

@@ -127,3 +127,42 @@ def test_batch_rejects_bad_input():
     with pytest.raises(corr.CorrError) as e:
         corr.corr_batch_set_mode(b.h, corr.CORR_BATCH_PERSISTENT)
     assert e.value.code == corr.CORR_ESTATE
+
+
+def test_branches_jobs_in_chunks_replay():
+    """Branch jobs keep their own tiles, several chunks each included: the
+    kernels add each chunk's offset to the input pointer they read from the
+    job's slot. Every replay, with the inputs moved to other addresses from
+    the second on, equals the single-job path with the same tiles, bit for
+    bit (same kernels on the same spectra)."""
+    jobs = [(8, 128, 200, "int8"), (12, 256, 300, "fp32"), (44, 256, 130, "fp16"), (16, 512, 70, "fp32")]
+    tiles = {0: dict(chunk_spectra=64, x_splits=1, f_group=4), 1: dict(chunk_spectra=128, x_splits=2, f_group=16),
+             2: dict(chunk_spectra=64, x_splits=1, f_group=2), 3: dict(chunk_spectra=64, x_splits=2, f_group=1)}
+    inputs = _inputs(jobs, seed0=300)
+    singles = []
+    for j, (N, K, S, prec) in enumerate(jobs):
+        c = corr.Correlator(N, K, S, precision=prec, tiles=tiles[j])
+        c.process(inputs[j])
+        singles.append(c.read_cps_raw())
+        c.close()
+        _check_job(singles[j], N, K, S, prec, inputs[j])
+    b = corr.Batch(jobs, tiles=tiles, mode="branches")
+    moved = [x.clone() for x in inputs]
+    for rep in range(3):
+        b.process(inputs if rep == 0 else moved)
+        torch.cuda.synchronize()
+        print(f"\n[branches in chunks] replay {rep}", flush=True)
+        for j in range(len(jobs)):
+            np.testing.assert_array_equal(b.read_cps_raw(j), singles[j], err_msg=f"replay {rep} job {j}")
+    b.close()
+
+
+def test_persistent_mode_rejects_chunked_tiles():
+    """The persistent kernel runs each job as one chunk with its own F group:
+    other tiles fail at the first process, before any launch."""
+    b = corr.Batch([(8, 128, 200, "fp32")], tiles={0: dict(chunk_spectra=64)}, mode="persistent")
+    x = torch.zeros(200 * 8 * 128, dtype=torch.uint8, device="cuda")
+    with pytest.raises(corr.CorrError) as e:
+        b.process([x])
+    assert e.value.code == corr.CORR_EINVAL
+    b.close()
