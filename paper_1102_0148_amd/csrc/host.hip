@@ -895,13 +895,14 @@ namespace {
 
 constexpr int kBatchBranches = 4;
 
-// Branches mode: plan every job as one chunk with its own kernels, and
-// capture them into one graph whose jobs run on kBatchBranches parallel
-// branches, dealt round-robin in order of decreasing work.  (Dealing each job
-// to the branch with the least work so far measured slower: it lined the
-// small jobs up behind one another on one branch instead of beside the large
-// ones' tails.)  The kernels read each job's input pointer from b->in_ptrs,
-// which corr_batch_process rewrites before every replay.
+// Branches mode: plan every job with its own tiles and kernels, and capture
+// them into one graph whose jobs run on up to kBatchBranches parallel
+// branches, in order of decreasing work (fp32 jobs on one branch of their
+// own, the others dealt round-robin).  (Dealing each job to the branch with
+// the least work so far measured slower: it lined the small jobs up behind
+// one another on one branch instead of beside the large ones' tails.)  The
+// kernels read each job's input pointer from b->in_ptrs, which
+// corr_batch_process rewrites before every replay.
 int batch_build_branches(corr_ctx *b) {
     HIP_TRY(hipSetDevice(b->device), "hipSetDevice");
     const int nj = (int)b->jobs.size();
@@ -920,7 +921,25 @@ int batch_build_branches(corr_ctx *b) {
     std::vector<int> order(nj);
     for (int j = 0; j < nj; ++j) order[j] = j;
     std::sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
-    const int nbr = std::min(kBatchBranches, nj);
+    // fp32 jobs (X-stage bound by the MFMA rate, F-stage by HBM writes) slow
+    // one another down side by side: the 12-job fp32 batch took 4.45 ms on
+    // four branches and 4.34 ms on one.  The int8 batch took 2.30 ms on four
+    // and 2.97 ms on one.  So the fp32 jobs share one branch, and the other
+    // jobs are dealt round-robin over the remaining branches.
+    int n_f32 = 0;
+    for (corr_ctx *h : b->jobs) n_f32 += h->prec == kFP32;
+    const int f32_br = n_f32 ? 1 : 0;
+    const int nbr = f32_br + std::min(kBatchBranches - f32_br, nj - n_f32);
+    std::vector<int> branch_of(nj);
+    for (int i = 0, next = 0; i < nj; ++i) {
+        const int j = order[i];
+        if (b->jobs[j]->prec == kFP32) {
+            branch_of[j] = 0;
+        } else {
+            branch_of[j] = f32_br + next;
+            next = (next + 1) % (nbr - f32_br);
+        }
+    }
     HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
     for (int i = 0; i < nbr; ++i) {
         hipStream_t s = nullptr;
@@ -938,7 +957,7 @@ int batch_build_branches(corr_ctx *b) {
         HIP_TRY(hipEventRecord(b->br_events[0], b->cap_stream), "hipEventRecord(fork)");
         for (hipStream_t s : b->br_streams) HIP_TRY(hipStreamWaitEvent(s, b->br_events[0], 0), "hipStreamWaitEvent");
         for (int i = 0; i < nj; ++i) {
-            int rc = process_one(b->jobs[order[i]], nullptr, b->br_streams[i % nbr]);
+            int rc = process_one(b->jobs[order[i]], nullptr, b->br_streams[branch_of[order[i]]]);
             if (rc) return rc;
         }
         for (int i = 0; i < nbr; ++i) {
