@@ -299,9 +299,10 @@ def x_mfma(metrics, N, K, S, prec, x_ms):
             "frac": round(rate / peak, 4)}
 
 
-def cpu_baseline(inputs_cpu_sample, S_sample, S_one_thread):
-    """The oracle timed on the host's cores, then on one thread over a smaller
-    sample (the analogue of the paper's multicore-against-one-thread figure)."""
+def cpu_baseline(inputs_cpu_sample, S_sample, S_one_thread, S_large=0):
+    """The oracle timed on the host's cores; then on the large-N workload over
+    a small sample; then on one thread over a smaller sample (the analogue of
+    the paper's multicore-against-one-thread figure)."""
     import oracle
     threads = oracle.get_threads()
     t0 = time.perf_counter()
@@ -311,6 +312,18 @@ def cpu_baseline(inputs_cpu_sample, S_sample, S_one_thread):
     out = {"value": round(rate, 3), "unit": "antenna-MS/s", "cores": threads, "kind": "oracle",
            "sample": f"first {S_sample} spectra of integration 1 (N={N_ANT}, 2K={TWO_K}), "
                      f"float64 FFT + pairwise CMAC, {dt:.1f} s"}
+    if S_large > 0:
+        # the X-dominated case: the N = 256, 1024-point workload's first
+        # S_large spectra (linear in spectra, so the rate stands for the whole)
+        import synth
+        NL, two_kl = 256, 1024
+        xl = synth.packed(synth.recipe_sources(N=NL, two_k=two_kl, seed=4), 0, S_large).numpy()
+        t0 = time.perf_counter()
+        oracle.correlate(xl, S_large, NL, two_kl // 2)
+        dtl = time.perf_counter() - t0
+        out["large_n"] = {"value": round(NL * S_large * two_kl / dtl / 1e6, 3),
+                          "x_gops": round(8.0 * NL * (NL + 1) / 2 * (two_kl // 2) * S_large / dtl / 1e9, 2),
+                          "sample": f"first {S_large} spectra of the N={NL}, 2K={two_kl} workload, {dtl:.1f} s"}
     if S_one_thread > 0:
         oracle.set_threads(1)
         try:
@@ -333,6 +346,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-spectra", type=int, default=65536)
     ap.add_argument("--cpu-spectra-one-thread", type=int, default=4096)
+    ap.add_argument("--cpu-spectra-large-n", type=int, default=128)
     ap.add_argument("--forms", default="fp32,fp16,int8,int16")
     ap.add_argument("--no-extra", action="store_true", help="skip the large-N and batch workloads")
     ap.add_argument("--copy-probe", action="store_true",
@@ -447,7 +461,8 @@ def main():
         import synth
         recipe = synth.recipe_plain(N=N_ANT, two_k=TWO_K, rho=0.05, seed=1)
         sample = synth.packed(recipe, 0, args.cpu_spectra, device="cuda").cpu().numpy()
-        out["cpu_baseline"] = cpu_baseline(sample, args.cpu_spectra, min(args.cpu_spectra_one_thread, args.cpu_spectra))
+        out["cpu_baseline"] = cpu_baseline(sample, args.cpu_spectra, min(args.cpu_spectra_one_thread, args.cpu_spectra),
+                                           args.cpu_spectra_large_n)
     print(json.dumps(out))
 
 
