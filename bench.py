@@ -346,7 +346,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-spectra", type=int, default=65536)
     ap.add_argument("--cpu-spectra-one-thread", type=int, default=4096)
-    ap.add_argument("--cpu-spectra-large-n", type=int, default=128)
+    ap.add_argument("--cpu-spectra-large-n", type=int, default=1024)
     ap.add_argument("--forms", default="fp32,fp16,int8,int16")
     ap.add_argument("--no-extra", action="store_true", help="skip the large-N and batch workloads")
     ap.add_argument("--copy-probe", action="store_true",
