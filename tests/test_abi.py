@@ -82,6 +82,28 @@ def test_record_layout_round_trip(prec, N, S):
         np.testing.assert_array_equal(rec[tg:tg + n].astype(np.float32), spec[:n, 2, 3].imag)
 
 
+@pytest.mark.parametrize("N,S", [(5, 7), (44, 33), (70, 9)])
+def test_int16_record_layout_round_trip(N, S):
+    """int16 records: codes within +-32512 round-trip through the base-255
+    digit layout [h of re x4][h of im x4][l of re x4][l of im x4], and one
+    record checked by hand."""
+    K = 8
+    rng = np.random.default_rng(1600 + N)
+    spec = rng.integers(-32512, 32513, (S, N, K, 2)).astype(np.int16)
+    spec[0, 0, 0] = (32512, -32512)
+    buf = corr.spectra_to_records(spec, corr.CORR_INT16)
+    a_pad = corr.a_pad_of(N)
+    ntq = ((S + 3) // 4 + 15) // 16 * 16
+    assert buf.size == K * ntq * a_pad * 16
+    np.testing.assert_array_equal(corr.records_to_spectra(buf, corr.CORR_INT16, N, K, S), spec)
+    rec = buf.view(np.int8).reshape(-1, K, 16, a_pad, 16)[0, 3, 0, 2].astype(np.int32)
+    n = min(4, S)
+    q = spec[:n, 2, 3].astype(np.int32)  # [t][re, im]
+    np.testing.assert_array_equal(255 * rec[0:n] + rec[8:8 + n], q[:, 0])
+    np.testing.assert_array_equal(255 * rec[4:4 + n] + rec[12:12 + n], q[:, 1])
+    assert np.abs(rec).max() <= 127
+
+
 def test_binding_constants_match_header():
     text = open(HEADER).read()
     for name in ("CORR_MAX_ANTENNAS", "CORR_MAX_CHANNELS", "CORR_CALIB_SPECTRA", "CORR_FRAME_HEADER_BYTES"):
