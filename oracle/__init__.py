@@ -57,7 +57,7 @@ def _load():
         "orc_vis_single": (i32, [P, i32, i32, i32, i32, i32, i32, P]),
         "orc_track": (i32, [P, i32, i32, i32, i32, P, P, P, P]),
         "orc_ingest": (i32, [P, i64, i64, ctypes.c_uint64, i32, i32, i32, i32, P, P, P]),
-        "orc_scales_n": (i32, [P, i32, i32, i32, i32, i32, ctypes.c_double, P]),
+        "orc_scales_n": (i32, [P, i32, i32, i32, i32, i32, ctypes.c_double, ctypes.c_double, P]),
         "orc_quantise16": (i32, [P, i32, i32, i32, P, P]),
         "orc_cmac_i64_16": (i32, [P, i32, i32, i32, i32, P]),
         "orc_set_threads": (i32, [i32]),
@@ -199,13 +199,18 @@ def ingest(frames: np.ndarray, n_frames: int, stride: int, first_seq: int, S: in
     return out, stats, int(wv[0])
 
 
-def scales_n(spec: np.ndarray, W: int, n_div: int, qmax: float = 127.0) -> np.ndarray:
-    """Scales over the first W spectra with the mean taken over n_div, for the
-    largest code qmax (127: int8, 32512: int16)."""
+# Largest code and the multiple of the rms it stands for, per requantised form
+FULL_SCALE = {"int8": (127.0, 4.0), "int16": (32512.0, 8.0)}
+
+
+def scales_n(spec: np.ndarray, W: int, n_div: int, form: str = "int8") -> np.ndarray:
+    """Scales of `form` ("int8" or "int16") over the first W spectra with the
+    mean power taken over n_div spectra."""
     S, N, K = spec.shape
+    qmax, clip = FULL_SCALE[form]
     pairs = _spec_pairs(spec)
     out = np.empty((N, K), dtype=np.float32)
-    _check(_load().orc_scales_n(_ptr(pairs), S, N, K, W, n_div, float(qmax), _ptr(out)), "orc_scales_n")
+    _check(_load().orc_scales_n(_ptr(pairs), S, N, K, W, n_div, qmax, clip, _ptr(out)), "orc_scales_n")
     return out
 
 

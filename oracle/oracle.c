@@ -36,10 +36,16 @@
  *   - bins 0..K-1 are kept (DC kept, Nyquist bin K dropped);
  *   - baselines include autos, upper triangle, row-major:
  *     bl(a,b) = a*N - a*(a-1)/2 + (b-a);
- *   - int8: rms over the first W spectra of the integration, per component:
- *     rms = sqrt(sum(re^2+im^2) / (2W)); sc = 127 / (4 rms) in float; a
- *     channel with zero power gets sc = 1; q = clamp(rint(float(x) * sc),
- *     -127, 127) with float arithmetic and ties to even.
+ *   - int8: rms over the first W spectra of the integration, per non-zero
+ *     component of the channel: a real-input transform's channel 0 (DC) has
+ *     no imaginary part, so rms = sqrt(sum(re^2) / W) there and
+ *     rms = sqrt(sum(re^2+im^2) / (2W)) in every other channel;
+ *     sc = 127 / (4 rms) in float; a channel with zero power gets sc = 1;
+ *     q = clamp(rint(float(x) * sc), -127, 127) with float arithmetic and
+ *     ties to even;
+ *   - int16: the same with the largest code 32512 standing for 8 rms (its
+ *     steps are 128 times finer than int8's and a Gaussian component clips
+ *     with probability about 1e-15), q clamped to +-32512.
  *
  * Parity status: every function here is pinned by the CPU test suite
  * (brute-force DFT, numpy's FFT, Parseval, Hermitian symmetry, exact integer
@@ -47,7 +53,7 @@
  * identical-input baselines, int64 == float64 on integer input; tracking:
  * the DFT shift theorem, quarter and half turns, common-phase invariance and
  * the removal of a delayed source's phase slope; int16: ties and clamp,
- * int64 sums against numpy, scales 256 times the int8 rule's; ingest:
+ * int64 sums against numpy, scales 128 times the int8 rule's; ingest:
  * hand-built order,
  * loss, repeats and every header fault, and the scales over received blocks
  * against the plain rule on the window without the lost blocks).  The int8
@@ -249,12 +255,19 @@ int orc_ingest(const uint8_t *frames, int64_t n_frames, int64_t stride, uint64_t
     return ORC_OK;
 }
 
-/* Scales for the largest code qmax (127 for int8, 32512 for int16) whose
- * mean power divides by n_div spectra (the ones received in the window; W
- * when none is lost); lost spectra are zero and add no power.  */
-int orc_scales_n(const double *spec, int S, int N, int K, int W, int n_div, double qmax, float *scales)
+/* Components of channel k that can be non-zero: the DC channel of a
+ * real-input transform is real, every other kept channel complex.  */
+static double components(int k) { return k == 0 ? 1.0 : 2.0; }
+
+/* Scales for a form whose largest code qmax stands for `clip` times the rms
+ * of one component (int8: 127 at 4 rms; int16: 32512 at 8 rms), the mean
+ * power dividing by n_div spectra (the ones received in the window; W when
+ * none is lost); lost spectra are zero and add no power.  */
+int orc_scales_n(const double *spec, int S, int N, int K, int W, int n_div, double qmax, double clip,
+                 float *scales)
 {
-    if (!spec || !scales || N < 1 || K < 1 || W < 1 || W > S || n_div < 0 || !(qmax > 0)) return ORC_EINVAL;
+    if (!spec || !scales || N < 1 || K < 1 || W < 1 || W > S || n_div < 0 || !(qmax > 0) || !(clip > 0))
+        return ORC_EINVAL;
     for (int a = 0; a < N; ++a) {
         for (int k = 0; k < K; ++k) {
             double p = 0.0;
@@ -263,7 +276,7 @@ int orc_scales_n(const double *spec, int S, int N, int K, int W, int n_div, doub
                 p += x[0] * x[0] + x[1] * x[1];
             }
             double sc = 1.0;
-            if (p > 0.0 && n_div > 0) sc = qmax / (4.0 * sqrt(p / (2.0 * n_div)));
+            if (p > 0.0 && n_div > 0) sc = qmax / (clip * sqrt(p / (components(k) * n_div)));
             scales[(int64_t)a * K + k] = (float)sc;
         }
     }
@@ -301,7 +314,8 @@ int orc_cmac_f64(const double *spec, int S, int N, int K, int full, double *vis)
     return ORC_OK;
 }
 
-/* int8 calibration: per-(antenna, channel) scale from the first W spectra.
+/* int8 calibration: per-(antenna, channel) scale from the first W spectra,
+ * full scale 127 at 4 times the rms of one non-zero component.
  * spec: [S][N][K][2] doubles; scales: [N][K] floats.  */
 int orc_scales(const double *spec, int S, int N, int K, int W, float *scales)
 {
@@ -315,7 +329,7 @@ int orc_scales(const double *spec, int S, int N, int K, int W, float *scales)
             }
             double sc = 1.0;
             if (p > 0.0) {
-                double rms = sqrt(p / (2.0 * W));
+                double rms = sqrt(p / (components(k) * W));
                 sc = 127.0 / (4.0 * rms);
             }
             scales[(int64_t)a * K + k] = (float)sc;

@@ -252,30 +252,59 @@ def test_quantise_rounding_and_saturation(orc):
 
 
 def test_scales_follow_rms_rule(orc):
-    """Constant-magnitude spectra: rms is known, so sc = 127 / (4 rms)."""
+    """Constant-magnitude spectra: the rms of each non-zero component is known,
+    so sc = 127 / (4 rms).  Channel 0 (DC of a real-input transform) has one
+    component, every other channel two."""
     S, N, K = 10, 2, 3
     spec = np.zeros((S, N, K), dtype=np.complex128)
-    spec[:, 0, :] = 3.0 + 4.0j          # |x|^2 = 25 -> per-component rms 5/sqrt(2)
-    spec[:, 1, 0] = 2.0                  # |x|^2 = 4  -> rms sqrt(2)
+    spec[:, 0, :] = 3.0 + 4.0j          # |x|^2 = 25: rms 5 in channel 0, 5/sqrt(2) elsewhere
+    spec[:, 1, 0] = 2.0                  # a real DC of constant magnitude: rms 2
     spec[5:, 1, 1] = 100.0               # outside a window of 5: zero power inside
     sc = orc.scales(spec, W=5)
-    np.testing.assert_allclose(sc[0], 127.0 / (4 * 5 / math.sqrt(2)), rtol=1e-7)
-    np.testing.assert_allclose(sc[1, 0], 127.0 / (4 * math.sqrt(2)), rtol=1e-7)
+    np.testing.assert_allclose(sc[0, 0], 127.0 / (4 * 5.0), rtol=1e-7)
+    np.testing.assert_allclose(sc[0, 1:], 127.0 / (4 * 5 / math.sqrt(2)), rtol=1e-7)
+    np.testing.assert_allclose(sc[1, 0], 127.0 / (4 * 2.0), rtol=1e-7)
     assert sc[1, 1] == 1.0 and sc[1, 2] == 1.0
+    # a constant real DC of 2 lands on code 127 / 4 = 31.75 -> 32, at a
+    # quarter of full scale, as a Gaussian component's rms does elsewhere
+    q = orc.quantise(spec[:, 1:, :1], sc[1:, :1])
+    np.testing.assert_array_equal(q[..., 0], 32)
+    np.testing.assert_array_equal(q[..., 1], 0)
+
+
+def _gauss_tail(c):
+    return 2 * (1 - ndtr(c))
 
 
 def test_int8_saturation_matches_gaussian_tail(orc):
     """With full scale at 4 rms, a Gaussian component saturates with probability
-    P(|z| > 4 * 127.5 / 127)."""
+    P(|z| > 4 * 127.5 / 127), in channels 1..K-1."""
     S, N, K = 1024, 4, 256
     r = synth.recipe_plain(N=N, two_k=2 * K, seed=6)
     spec = orc.spectra(synth.packed(r, 0, S).numpy(), S, N, K)
     sc = orc.scales(spec, W=S)
     q = orc.quantise(spec[:, :, 1:], sc[:, 1:])
     frac = np.mean(np.abs(q) == 127)
-    p = 2 * (1 - ndtr(4 * 127.5 / 127))
+    p = _gauss_tail(4 * 127.5 / 127)
     n = q.size
     assert abs(frac - p) < 6 * math.sqrt(p / n) + 1e-6
+
+
+def test_int8_dc_saturates_like_other_channels(orc):
+    """The DC bin of real samples is a real Gaussian: its one component must
+    clip at the same 4 rms as the others' (P ~ 6e-5), not at 4/sqrt(2) rms
+    (P ~ 4.7e-3), which dividing its power over two components would give."""
+    S, N, K = 8192, 4, 256
+    r = synth.recipe_plain(N=N, two_k=2 * K, seed=16)
+    spec = orc.spectra(synth.packed(r, 0, S).numpy(), S, N, K)
+    sc = orc.scales(spec, W=S)
+    q = orc.quantise(spec[:, :, :1], sc[:, :1])
+    assert np.all(q[..., 1] == 0)
+    frac = np.mean(np.abs(q[..., 0]) == 127)
+    p = _gauss_tail(4 * 127.5 / 127)
+    n = q[..., 0].size
+    assert abs(frac - p) < 6 * math.sqrt(p / n) + 1e-6
+    assert frac < _gauss_tail(4 / math.sqrt(2)) / 10
 
 
 def test_cmac_i64_exact(orc):
@@ -478,12 +507,79 @@ def test_cmac_i64_16_exact(orc):
     np.testing.assert_array_equal(v[..., 1], vi)
 
 
-def test_scales16_are_256_times_int8_scales(orc):
-    """32512 = 256 * 127, a power of two apart: the int16 rule's scales are
-    exactly 256 times the int8 rule's."""
+def test_scales16_are_128_times_int8_scales(orc):
+    """int16 puts 32512 at 8 rms, int8 127 at 4 rms: 32512 / 8 = 4064 =
+    128 * 127 / 4, a power of two apart, so the int16 rule's scales are
+    exactly 128 times the int8 rule's."""
     rng = np.random.default_rng(12)
     spec = rng.standard_normal((30, 3, 16)) * 40 + 1j * rng.standard_normal((30, 3, 16)) * 40
-    np.testing.assert_array_equal(orc.scales_n(spec, 20, 20, 32512.0), 256 * orc.scales(spec, 20))
+    spec[:, :, 0] = spec[:, :, 0].real
+    np.testing.assert_array_equal(orc.scales_n(spec, 20, 20, "int16"), 128 * orc.scales(spec, 20))
+    np.testing.assert_array_equal(orc.scales_n(spec, 20, 20, "int8"), orc.scales(spec, 20))
+
+
+def test_int16_closed_form_and_no_gaussian_clipping(orc):
+    """A constant real DC x lands on 32512 / 8 = 4064 exactly; constant 3 + 4i
+    elsewhere has rms 5 / sqrt(2), so 3 maps to rint(3 * 4064 sqrt(2) / 5).
+    On Gaussian spectra (2.6M components) nothing reaches +-32512: the clip
+    at 8 rms has probability ~1e-15 per component."""
+    S, N, K = 6, 1, 4
+    spec = np.zeros((S, N, K), dtype=np.complex128)
+    spec[:, 0, 0] = -7.25
+    spec[:, 0, 1:] = 3.0 + 4.0j
+    sc = orc.scales_n(spec, S, S, "int16")
+    q = orc.quantise16(spec, sc)
+    np.testing.assert_array_equal(q[:, 0, 0], [[-4064, 0]] * S)
+    want = [round(3 * 4064 * math.sqrt(2) / 5), round(4 * 4064 * math.sqrt(2) / 5)]
+    np.testing.assert_array_equal(q[:, 0, 1:], np.broadcast_to(want, (S, K - 1, 2)))
+    S, N, K = 1024, 5, 256
+    r = synth.recipe_plain(N=N, two_k=2 * K, seed=26)
+    spec = orc.spectra(synth.packed(r, 0, S).numpy(), S, N, K)
+    q = orc.quantise16(spec, orc.scales_n(spec, S, S, "int16"))
+    assert np.max(np.abs(q.astype(np.int32))) < 32512
+    # the largest code sits where the largest |z| of 2.6M Gaussian draws does,
+    # about 5 rms, i.e. 5 / 8 of full scale
+    assert 0.5 < np.max(np.abs(q.astype(np.int32))) / 32512 < 0.85
+
+
+def _descaled_error(orc, spec, N, K, q, sc, cmac):
+    v = cmac(q).astype(np.float64)
+    den = np.empty((orc.n_baselines(N), K))
+    bl = 0
+    for a in range(N):
+        for b in range(a, N):
+            den[bl] = sc[a].astype(np.float64) * sc[b]
+            bl += 1
+    vis = (v[..., 0] + 1j * v[..., 1]) / den
+    ref = orc.cmac_f64(spec)
+    auto = np.array([ref[orc.baseline_index(N, a, a)].real for a in range(N)])
+    err = np.zeros(K)
+    bl = 0
+    for a in range(N):
+        for b in range(a, N):
+            err = np.maximum(err, np.abs(vis[bl] - ref[bl]) / np.sqrt(auto[a] * auto[b]))
+            bl += 1
+    return err                      # per channel, coefficient units
+
+
+def test_requantised_error_follows_word_length(orc):
+    """Section 4 prescales before the conversion to a short type so that the
+    conversion costs little precision.  On the benchmark's accuracy input
+    (N = 44, 512-point, 1024 spectra, rho = 0.05) the de-scaled int16 result
+    is within 1e-4 of float64 in coefficient units, and int8's error (the
+    clip at 4 rms, which the word length forces) is no larger in channel 0
+    than elsewhere."""
+    N, K, S = 44, 256, 1024
+    r = synth.recipe_plain(N=N, two_k=2 * K, rho=0.05, seed=1)
+    spec = orc.spectra(synth.packed(r, 0, S).numpy(), S, N, K)
+    sc16 = orc.scales_n(spec, S, S, "int16")
+    e16 = _descaled_error(orc, spec, N, K, orc.quantise16(spec, sc16), sc16, orc.cmac_i64_16)
+    sc8 = orc.scales(spec, S)
+    e8 = _descaled_error(orc, spec, N, K, orc.quantise(spec, sc8), sc8, orc.cmac_i64)
+    print(f"\n  int16 {e16.max():.3g}; int8 channel 0 {e8[0]:.3g}, others {e8[1:].max():.3g}")
+    assert e16.max() <= 1e-4
+    assert e8[0] <= e8[1:].max()
+    assert e8.max() <= 1.5e-2
 
 
 def test_thread_count_leaves_results_unchanged(orc):
