@@ -294,9 +294,31 @@ def x_mfma(metrics, N, K, S, prec, x_ms):
     if x_ms <= 0:
         return None
     rate = metrics.x_mfma_ops(N, K, S, prec) / (x_ms * 1e-3) / 1e12
+    useful = metrics.x_ops(N, K, S) / (x_ms * 1e-3) / 1e12
     peak = metrics.MFMA_PEAK[prec]
     return {"issued": round(rate, 2), "peak": peak, "unit": "TFLOP/s" if prec.startswith("fp") else "TOPS",
-            "frac": round(rate / peak, 4)}
+            "frac": round(rate / peak, 4), "useful": round(useful, 2), "useful_frac": round(useful / peak, 4)}
+
+
+def cpu_identity():
+    """The host's CPU model and the logical CPUs this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    if not model:
+        import platform
+        model = platform.processor() or platform.machine()
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return model, avail
 
 
 def cpu_baseline(inputs_cpu_sample, S_sample, S_one_thread, S_large=0):
@@ -309,7 +331,9 @@ def cpu_baseline(inputs_cpu_sample, S_sample, S_one_thread, S_large=0):
     oracle.correlate(inputs_cpu_sample, S_sample, N_ANT, K)
     dt = time.perf_counter() - t0
     rate = N_ANT * S_sample * TWO_K / dt / 1e6
+    model, avail = cpu_identity()
     out = {"value": round(rate, 3), "unit": "antenna-MS/s", "cores": threads, "kind": "oracle",
+           "cpu_model": model, "cpus_available": avail, "threads_used": threads,
            "sample": f"first {S_sample} spectra of integration 1 (N={N_ANT}, 2K={TWO_K}), "
                      f"float64 FFT + pairwise CMAC, {dt:.1f} s"}
     if S_large > 0:

@@ -179,7 +179,8 @@ int corr_set_tracking(corr_handle h, const double *delay, const double *delay_ra
  * N(N+1)/2, layout [baseline][channel][re, im], in the units of the
  * unnormalised transform (INT8 and INT16 values are divided by s_a*s_b,
  * the two antennas' scales).  CORR_ESTATE if nothing was processed since the last
- * read.  */
+ * read, and for INT8 / INT16 sums that no calibration has scaled (spectra
+ * given to corr_process_spectra only: read those with corr_read_cps_raw).  */
 int corr_read_cps(corr_handle h, float *out);
 
 /* As corr_read_cps but the float64 buffer as it is: for INT8 and INT16 the
@@ -193,7 +194,9 @@ int corr_read_cps_async(corr_handle h, double *dst, void *stream);
 
 /* INT8 and INT16 only: the scales [N][K] (float) used by the last
  * integration.  out: HOST pointer.  Waits for the handle's stream.
- * CORR_ESTATE for the float forms or before the first integration.  */
+ * CORR_ESTATE for the float forms, and before the first calibrated
+ * integration (corr_process or a batch replay; corr_get_tiles and
+ * corr_process_spectra calibrate nothing).  */
 int corr_read_scales(corr_handle h, float *out);
 
 /* Bytes of spectra in the library layout for n_spectra spectra (the size of
@@ -212,7 +215,11 @@ size_t corr_spectra_bytes(corr_handle h, int n_spectra);
 /* X-stage + dump only, on n_spectra spectra already in the library layout
  * (DEVICE pointer, corr_spectra_bytes(h, n_spectra) bytes).  Adds into the
  * integration buffer like corr_process; INT8 and INT16 spectra are taken as
- * given (no calibration).  */
+ * given (no calibration).  The x_splits of the handle's tiles were sized for
+ * chunk_spectra; a longer n_spectra runs as consecutive ranges of whole time
+ * blocks, each short enough that no partial sums more spectra than its form
+ * allows (2048 for FP32, 16384 for FP16 and INT16; the INT16 bound keeps the
+ * int32 digit sums exact).  */
 int corr_process_spectra(corr_handle h, const void *spectra, int n_spectra, void *stream);
 
 /* Copy the spectra of the last chunk the F-stage produced (library layout)

@@ -144,7 +144,7 @@ __global__ __launch_bounds__(256, 2) void batch_kernel(const BJob *jobs, const u
             }
             case BI_SCALES:
                 for (int e = it.a0 + (int)threadIdx.x; e < it.a1; e += 256)
-                    j.scales[e] = scale_one(j.p.power, j.nparts, j.p.a_pad, j.K, j.W, e);
+                    j.scales[e] = scale_one(j.p.power, j.nparts, j.p.a_pad, j.K, j.W, e, kI8CodesPerRms);
                 break;
             case BI_F: {
                 FArgs fa = j.f;

@@ -17,6 +17,12 @@ __host__ __device__ constexpr bool is_quant(int prec) { return prec == kINT8 || 
 // int16 values: |q| <= 32512 = 255 * 127 + 127, each stored as two int8
 // digits in base 255, q = 255 h + l with h, l in [-127, 127]
 constexpr int kI16Max = 32512;
+// Calibration: the largest code stands for a multiple of the rms of one
+// component over the window, 4 rms for int8 (127 / 4 codes per rms) and
+// 8 rms for int16 (32512 / 8 = 4064), where a Gaussian component clips with
+// probability about 1e-15 and the 16-bit word buys precision rather than range.
+constexpr float kI8CodesPerRms = 127.0f / 4.0f;
+constexpr float kI16CodesPerRms = (float)kI16Max / 8.0f;
 // spectra one int16 partial may sum: every digit sum stays below 2^31 (the
 // cross sum adds 4 digit products per spectrum: 4 * 16384 * 127^2 < 2^31)
 constexpr int kI16SplitSpectra = 16384;
@@ -142,9 +148,10 @@ hipError_t launch_dump(int prec, const void *partial, double2 *acc, int nsplit, 
                        hipStream_t st);
 // scales[a][f] from power partials summed in order over nparts; the mean
 // power divides by W spectra, or by *w_valid when given (the spectra of the
-// window that arrived, counted on the device by the frame ingest).
+// window that arrived, counted on the device by the frame ingest), and by the
+// channel's non-zero components (1 for DC, else 2); scale = codes_per_rms / rms.
 hipError_t launch_scales(const float *power, int nparts, int N, int a_pad, int K, int W,
-                         const unsigned *w_valid, float qmax, float *scales, hipStream_t st);
+                         const unsigned *w_valid, float codes_per_rms, float *scales, hipStream_t st);
 // dst[bl][f] = acc[f][bl] (raw layout), then acc = 0.
 hipError_t launch_finalize(double2 *acc, double2 *dst, int K, int nb, hipStream_t st);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st);

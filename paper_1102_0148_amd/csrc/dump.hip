@@ -13,11 +13,11 @@ __global__ __launch_bounds__(256) void dump_kernel(const P *partial, double2 *ac
 }
 
 __global__ __launch_bounds__(256) void scales_kernel(const float *power, int nparts, int N, int a_pad,
-                                                     int K, int W, const unsigned *w_valid, float qmax,
-                                                     float *scales) {
+                                                     int K, int W, const unsigned *w_valid,
+                                                     float codes_per_rms, float *scales) {
     const int e = blockIdx.x * 256 + threadIdx.x;
     const int w = w_valid ? (int)*w_valid : W;
-    if (e < N * K) scales[e] = scale_one(power, nparts, a_pad, K, w, e, qmax);
+    if (e < N * K) scales[e] = scale_one(power, nparts, a_pad, K, w, e, codes_per_rms);
 }
 
 // dst[bl][f] = acc[f][bl]; acc = 0
@@ -53,10 +53,10 @@ hipError_t launch_dump(int prec, const void *partial, double2 *acc, int nsplit, 
 }
 
 hipError_t launch_scales(const float *power, int nparts, int N, int a_pad, int K, int W,
-                         const unsigned *w_valid, float qmax, float *scales, hipStream_t st) {
+                         const unsigned *w_valid, float codes_per_rms, float *scales, hipStream_t st) {
     const int grid = (N * K + 255) / 256;
-    hipLaunchKernelGGL(scales_kernel, dim3(grid), dim3(256), 0, st, power, nparts, N, a_pad, K, W, w_valid, qmax,
-                       scales);
+    hipLaunchKernelGGL(scales_kernel, dim3(grid), dim3(256), 0, st, power, nparts, N, a_pad, K, W, w_valid,
+                       codes_per_rms, scales);
     return hipGetLastError();
 }
 

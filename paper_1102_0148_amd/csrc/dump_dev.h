@@ -20,18 +20,20 @@ __device__ __forceinline__ void dump_one(const P *partial, double2 *acc, int nsp
 }
 
 // Scale of (antenna, channel) e = ant * K + c: the power over the window is
-// summed over its nparts partials in order; rms per component is
-// sqrt(P / (2W)); scale = qmax / (4 rms), qmax being the largest code (127
-// for int8, 32512 for int16); a channel with no power keeps 1.
+// summed over its nparts partials in order; rms is that of one non-zero
+// component, sqrt(P / W) in channel 0 (a real-input transform's DC has no
+// imaginary part) and sqrt(P / (2W)) elsewhere; scale = codes_per_rms / rms,
+// the form's largest code over the rms multiple it stands for (int8: 127 at
+// 4 rms; int16: 32512 at 8 rms); a channel with no power keeps 1.
 __device__ __forceinline__ float scale_one(const float *power, int nparts, int a_pad, int K, int W, int e,
-                                           float qmax = 127.0f) {
+                                           float codes_per_rms) {
     const int ant = e / K, c = e % K;
     float p = 0.0f;
     for (int i = 0; i < nparts; ++i) p += power[((int64_t)i * a_pad + ant) * K + c];
     float sc = 1.0f;
     if (p > 0.0f && W > 0) {
-        const float rms = sqrtf(p / (2.0f * (float)W));
-        sc = qmax / (4.0f * rms);
+        const float rms = sqrtf(p / ((c == 0 ? 1.0f : 2.0f) * (float)W));
+        sc = codes_per_rms / rms;
     }
     return sc;
 }

@@ -121,6 +121,7 @@ struct corr_ctx {
     float2 *tw = nullptr;
     float *scales = nullptr;
     float *power = nullptr;
+    bool scales_valid = false;  // a calibration has been enqueued into `scales`
     int2 *regions = nullptr;
     unsigned long long *sat = nullptr;
     unsigned *fticket = nullptr;  // F-stage tile-chunk counters
@@ -378,9 +379,10 @@ int calibrate(corr_ctx *h, const uint8_t *in, hipStream_t st) {
     HIP_TRY(launch_fstage(h->K, kFP32, gp, 1, fa, fa.ngroups * nparts, st), "calibration launch");
     // after a frame ingest, the spectra of the window that arrived
     const unsigned *w_valid = h->ingest_pending ? h->ingest_ctr + 3 : nullptr;
-    const float qmax = h->prec == kINT16 ? (float)kI16Max : 127.0f;
-    HIP_TRY(launch_scales(h->power, nparts, h->N, h->a_pad, h->K, W, w_valid, qmax, h->scales, st),
+    const float fs = h->prec == kINT16 ? kI16CodesPerRms : kI8CodesPerRms;
+    HIP_TRY(launch_scales(h->power, nparts, h->N, h->a_pad, h->K, W, w_valid, fs, h->scales, st),
             "scales launch");
+    h->scales_valid = true;
     timer_end(h, st);
     return CORR_OK;
 }
@@ -460,6 +462,8 @@ int descale_to_float(corr_ctx *h, const double *raw, float *out) {
         for (int64_t i = 0; i < 2 * n; ++i) out[i] = (float)raw[i];
         return CORR_OK;
     }
+    if (!h->scales_valid)
+        return fail(CORR_ESTATE, "no calibration yet: these sums are in code units (read them with corr_read_cps_raw)");
     std::vector<float> sc((size_t)h->N * h->K);
     HIP_TRY(hipMemcpy(sc.data(), h->scales, sc.size() * sizeof(float), hipMemcpyDeviceToHost), "hipMemcpy(scales)");
     int64_t bl = 0;
@@ -743,8 +747,8 @@ int corr_read_cps_async(corr_handle hh, double *dst, void *stream) {
 int corr_read_scales(corr_handle hh, float *out) {
     corr_ctx *h = single(hh);
     if (!h || !out) return fail(CORR_EINVAL, "invalid handle or out");
-    if (!is_quant(h->prec) || !h->scales)
-        return fail(CORR_ESTATE, "scales exist only for INT8 / INT16 after processing");
+    if (!is_quant(h->prec) || !h->scales_valid)
+        return fail(CORR_ESTATE, "scales exist only for INT8 / INT16 once an integration has been calibrated");
     HIP_TRY(hipStreamSynchronize(h->last_stream), "hipStreamSynchronize");
     HIP_TRY(hipMemcpy(out, h->scales, (size_t)h->N * h->K * sizeof(float), hipMemcpyDeviceToHost),
             "hipMemcpy(scales)");
@@ -771,9 +775,21 @@ int corr_process_spectra(corr_handle hh, const void *spectra, int n_spectra, voi
     hipStream_t st = (hipStream_t)stream;
     h->started = true;
     h->last_stream = st;
-    const int ntq = round_up((n_spectra + h->TG - 1) / h->TG, h->prec == kINT16 ? 8 : 4);
-    rc = launch_x_and_dump(h, (const uint4 *)spectra, ntq, ntq / 4, st);
-    if (rc) return rc;
+    // Ranges of whole time blocks, each at most x_splits times the spectra one
+    // partial may sum in this form (float accuracy, exact int16 digit sums):
+    // the splits were sized for chunk_spectra, and n_spectra may be longer.
+    const int cap = h->prec == kFP32 ? kF32SplitSpectra
+                  : h->prec == kFP16 ? kF16SplitSpectra
+                  : h->prec == kINT16 ? kI16SplitSpectra : 65536;
+    const int64_t tb_spectra = (int64_t)kTQB * h->TG;
+    const int64_t range = std::max<int64_t>(tb_spectra, (int64_t)h->tiles.x_splits * cap / tb_spectra * tb_spectra);
+    for (int64_t s0 = 0; s0 < n_spectra; s0 += range) {
+        const int n = (int)std::min<int64_t>(range, n_spectra - s0);
+        const int ntq = round_up((n + h->TG - 1) / h->TG, h->prec == kINT16 ? 8 : 4);
+        const uint4 *base = (const uint4 *)spectra + (s0 / tb_spectra) * h->K * kTQB * h->a_pad;
+        rc = launch_x_and_dump(h, base, ntq, ntq / 4, st);
+        if (rc) return rc;
+    }
     h->accumulated += n_spectra;
     return CORR_OK;
 }
@@ -1159,6 +1175,8 @@ int corr_batch_process(corr_handle b, const void *const *packed, void *stream) {
     HIP_TRY(hipGraphLaunch(b->gexec, st), "hipGraphLaunch");
     b->last_stream = st;
     for (corr_ctx *h : b->jobs) {
+        // both modes calibrate every requantised job in each replay
+        if (is_quant(h->prec)) h->scales_valid = true;
         h->started = true;
         h->last_stream = st;
         h->accumulated += h->S;

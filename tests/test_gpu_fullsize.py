@@ -70,9 +70,8 @@ def test_full_integration_sampled_baselines(prec):
     diff = q.astype(np.int32) - qref.astype(np.int32)
     assert np.max(np.abs(diff)) <= 1
     assert np.mean(diff != 0) <= (1e-3 if prec == "int8" else 5e-3)
-    qmax = 127.0 if prec == "int8" else 32512.0
     W = corr.CORR_CALIB_SPECTRA
-    np.testing.assert_allclose(scales[ANTS], oracle.scales_n(spec, W, W, qmax), rtol=1e-5)
+    np.testing.assert_allclose(scales[ANTS], oracle.scales_n(spec, W, W, prec), rtol=1e-5)
 
 
 def _sel_codes_n(buf, precision, N_, K_, S_, ants):
@@ -114,34 +113,45 @@ def test_large_n_full_size_sampled_baselines(prec):
     np.testing.assert_array_equal(raw[rows], oracle.cmac_i64(q).astype(np.float64))
 
 
-def test_batch_full_size_sampled_baselines():
+@pytest.mark.parametrize("mode", ["branches", "persistent"])
+def test_batch_full_size_sampled_baselines(mode):
     """The 12-job batch of the benchmark (16384 spectra per job, int8 and
-    fp32 alternating), in its default mode: every job's baselines among its
-    first, a middle and its last antenna against the oracle."""
+    fp32 alternating) with the autotuner's tiles, in both modes: the
+    persistent kernel then runs its tuned x_splits and F items of 16-64
+    tiles.  Every job's baselines among its first, a middle and its last
+    antenna are checked: fp32 jobs against the float64 oracle; int8 jobs
+    first bit for bit against a single-job correlator of the same shape
+    (same calibration, so the same scales and codes), then bit for bit
+    against the integer oracle on that correlator's exported codes."""
     recipes = synth.batch_jobs(12, seed=3)
     S_ = 16384
     jobs = [(r.N, r.K, S_, "fp32" if j % 2 == 0 else "int8") for j, r in enumerate(recipes)]
     xs = [synth.packed(r, 0, S_, device="cuda").contiguous() for r in recipes]
-    b = corr.Batch(jobs, tiles="auto")
+    print(f"\n[batch full size] {mode}", flush=True)
+    b = corr.Batch(jobs, tiles="auto", mode=mode)
     b.process(xs)
     for j, (r, (N_, K_, _, prec)) in enumerate(zip(recipes, jobs)):
         ants = sorted({0, N_ // 2, N_ - 1})
         raw = b.read_cps_raw(j)
-        spec = oracle.spectra(xs[j][:, ants, :].cpu().numpy(), S_, len(ants), K_)
         rows = [oracle.baseline_index(N_, a, c) for i, a in enumerate(ants) for c in ants[i:]]
         if prec == "fp32":
+            spec = oracle.spectra(xs[j][:, ants, :].cpu().numpy(), S_, len(ants), K_)
             err = coef_error(raw_to_complex(raw)[rows], oracle.cmac_f64(spec), len(ants))
-            print(f"\n  job {j} N={N_} K={K_} fp32: {err:.3g}", flush=True)
+            print(f"  job {j} N={N_} K={K_} fp32: {err:.3g}", flush=True)
             assert err <= TOL[corr.CORR_FP32]
-        else:
-            # exact integers in quantised units, and close to float64 once de-scaled
-            assert np.array_equal(raw[rows], np.round(raw[rows]))
-            sc = b.read_scales(j)[ants]
-            den = np.array([sc[i].astype(np.float64) * sc[k] for i in range(len(ants)) for k in range(i, len(ants))])
-            v = raw_to_complex(raw)[rows] / den
-            err = coef_error(v, oracle.cmac_f64(spec), len(ants))
-            print(f"\n  job {j} N={N_} K={K_} int8 de-scaled: {err:.3g}", flush=True)
-            assert err <= 3e-2
+            continue
+        single = corr.Correlator(N_, K_, S_, precision="int8", tiles=dict(chunk_spectra=S_))
+        single.process(xs[j])
+        buf, n = single.debug_read_spectra()
+        assert n == S_
+        np.testing.assert_array_equal(b.read_scales(j), single.read_scales())
+        np.testing.assert_array_equal(raw, single.read_cps_raw(), err_msg=f"job {j}: batch != single job")
+        q = _sel_codes_n(buf, corr.CORR_INT8, N_, K_, S_, ants)
+        np.testing.assert_array_equal(raw[rows], oracle.cmac_i64(q).astype(np.float64))
+        print(f"  job {j} N={N_} K={K_} int8: bit-exact", flush=True)
+        single.close()
+        del buf
+    b.close()
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp16", "int8", "int16"])

@@ -72,7 +72,6 @@ def test_ingest_calibration_counts_received_spectra(prec):
     spectra received; the next integration without ingest divides by W again."""
     N, K, S, first = 16, 256, 1500, 0
     code = corr.PRECISIONS[prec]
-    qmax = 127.0 if prec == "int8" else 32512.0
     cmac = oracle.cmac_i64 if prec == "int8" else oracle.cmac_i64_16
     _, frames = _scenario(S, N, K, first, seed=9, lose=0.2)
     n, stride = frames.shape
@@ -85,13 +84,13 @@ def test_ingest_calibration_counts_received_spectra(prec):
     W = min(S, corr.CORR_CALIB_SPECTRA)
     assert 0 < wv < W
     spec = oracle.spectra(ref_packed, S, N, K)
-    np.testing.assert_allclose(scales, oracle.scales_n(spec, W, wv, qmax), rtol=1e-5)
+    np.testing.assert_allclose(scales, oracle.scales_n(spec, W, wv, prec), rtol=1e-5)
     buf, m = c.debug_read_spectra()
     q = corr.records_to_spectra(buf, code, N, K, m)
     np.testing.assert_array_equal(raw, cmac(q).astype(np.float64))
     # the next integration is not an ingested one: the plain rule again
     c.process(out)
-    np.testing.assert_allclose(c.read_scales(), oracle.scales_n(spec, W, W, qmax), rtol=1e-5)
+    np.testing.assert_allclose(c.read_scales(), oracle.scales_n(spec, W, W, prec), rtol=1e-5)
     c.read_cps_raw()
 
 

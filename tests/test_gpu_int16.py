@@ -49,7 +49,7 @@ def test_int16_end_to_end(N, K, S):
     np.testing.assert_array_equal(raw, oracle.cmac_i64_16(q_gpu).astype(np.float64))
     spec = oracle.spectra(packed.numpy(), S, N, K)
     W = min(S, corr.CORR_CALIB_SPECTRA)
-    np.testing.assert_allclose(scales, oracle.scales_n(spec, W, W, QMAX), rtol=1e-5)
+    np.testing.assert_allclose(scales, oracle.scales_n(spec, W, W, "int16"), rtol=1e-5)
     q_ref = oracle.quantise16(spec, scales)
     diff = q_gpu.astype(np.int32) - q_ref.astype(np.int32)
     assert np.max(np.abs(diff)) <= 1
@@ -58,11 +58,13 @@ def test_int16_end_to_end(N, K, S):
     assert np.mean(diff != 0) <= 5e-3
     # physical units: the de-scaled result equals the oracle's own int16
     # result under the same rule (the codes differ by at most one in a few of
-    # a million values); its distance from float64 is the rule's clipping at
-    # 4 rms (rms from the calibration window), reported, not bounded
+    # a thousand values), and with full scale at 8 rms nothing clips, so it is
+    # within 1e-4 of float64: the 16-bit word's rounding, largest in channels
+    # 0 and K/2, whose values are Gaussian integers that a scale just off an
+    # integer maps to codes with one coherent rounding error
     c.process(packed.cuda())
     vis = c.read_cps()
-    sc_ref = oracle.scales_n(spec, W, W, QMAX)
+    sc_ref = oracle.scales_n(spec, W, W, "int16")
     q_own = oracle.quantise16(spec, sc_ref)
     v16 = oracle.cmac_i64_16(q_own).astype(np.float64)
     den = np.empty((oracle.n_baselines(N), K))
@@ -74,8 +76,33 @@ def test_int16_end_to_end(N, K, S):
     ref16 = (v16[..., 0] + 1j * v16[..., 1]) / den
     ref64 = oracle.cmac_f64(spec)
     err = coef_error(vis, ref16, N)
-    print(f"  de-scaled vs the oracle's int16: {err:.3g}; vs float64: {coef_error(vis, ref64, N):.3g}", flush=True)
+    err64 = coef_error(vis, ref64, N)
+    print(f"  de-scaled vs the oracle's int16: {err:.3g}; vs float64: {err64:.3g}", flush=True)
     assert err <= 1e-4
+    assert err64 <= 1e-4
+
+
+def test_int16_process_spectra_longer_than_its_splits():
+    """corr_process_spectra on more spectra than the handle's splits were
+    sized for (chunk 64, one split): 40000 spectra of extreme codes would
+    carry a digit cross sum of 4 * 40000 * 127^2 > 2^31 in one partial; the
+    library runs them as ranges of at most 16384 spectra per split, so the
+    sums stay exact."""
+    N, K, S = 8, 128, 40000
+    rng = np.random.default_rng(77)
+    q = rng.integers(-QMAX, QMAX + 1, (S, N, K, 2)).astype(np.int16)
+    q[:, :3] = QMAX          # antennas 0-2 at the largest code throughout
+    q[:, 3] = -QMAX
+    buf = torch.from_numpy(corr.spectra_to_records(q, corr.CORR_INT16)).cuda()
+    c = corr.Correlator(N, K, S, precision="int16", tiles=dict(chunk_spectra=64, x_splits=1))
+    c.process_spectra(buf, S)
+    raw = c.read_cps_raw()
+    np.testing.assert_array_equal(raw, oracle.cmac_i64_16(q).astype(np.float64))
+    # no calibration has run: there are no scales to read or de-scale with
+    with pytest.raises(corr.CorrError) as e:
+        c.read_scales()
+    assert e.value.code == corr.CORR_ESTATE
+    c.close()
 
 
 def test_int16_limits():

@@ -340,6 +340,24 @@ def test_fp16_x_stage_on_oracle_spectra(N, K, S):
     assert coef_error(raw, oracle.cmac_f64(half), N) <= 1e-5
 
 
+def test_fp32_process_spectra_longer_than_its_splits():
+    """corr_process_spectra on 5000 spectra with tiles sized for chunks of 64
+    (one split): run as ranges of at most 2048 spectra per partial, so the
+    float error stays within the fp32 tolerance."""
+    N, K, S = 12, 128, 5000
+    rng = np.random.default_rng(5)
+    common = rng.standard_normal((S, 1, K)) + 1j * rng.standard_normal((S, 1, K))
+    spec = 40 * (rng.standard_normal((S, N, K)) + 1j * rng.standard_normal((S, N, K)) + 0.6 * common)
+    spec = spec.real.astype(np.float32).astype(np.float64) + 1j * spec.imag.astype(np.float32).astype(np.float64)
+    buf = torch.from_numpy(corr.spectra_to_records(spec, corr.CORR_FP32)).cuda()
+    c = corr.Correlator(N, K, S, tiles=dict(chunk_spectra=64, x_splits=1))
+    c.process_spectra(buf, S)
+    raw = raw_to_complex(c.read_cps_raw())
+    err = coef_error(raw, oracle.cmac_f64(spec), N)
+    print(f"\n[fp32 long process_spectra] coefficient error {err:.3g}", flush=True)
+    assert err <= TOL[corr.CORR_FP32]
+
+
 # ------------------------------------------------------------------ state errors
 
 def test_state_errors():
@@ -358,6 +376,10 @@ def test_state_errors():
     assert e.value.code == corr.CORR_ESTATE
     c.read_cps_raw()
     ci = corr.Correlator(N, K, S, precision="int8")
+    ci.tiles()          # plans (allocates the scales) but calibrates nothing
+    with pytest.raises(corr.CorrError) as e:
+        ci.read_scales()
+    assert e.value.code == corr.CORR_ESTATE
     ci.process(packed)
     with pytest.raises(corr.CorrError) as e:
         ci.process(packed)

@@ -79,7 +79,6 @@ def test_tracked_integer_forms(prec):
     the GPU's own codes."""
     N, K, S = 44, 256, 200
     code = corr.PRECISIONS[prec]
-    qmax = 127.0 if prec == "int8" else 32512.0
     quantise = oracle.quantise if prec == "int8" else oracle.quantise16
     cmac = oracle.cmac_i64 if prec == "int8" else oracle.cmac_i64_16
     packed = synth.packed(synth.recipe_plain(N=N, two_k=2 * K, seed=12), 0, S).contiguous()
@@ -94,7 +93,7 @@ def test_tracked_integer_forms(prec):
     np.testing.assert_array_equal(raw, cmac(q_gpu).astype(np.float64))
     spec = oracle.spectra(packed.numpy(), S, N, K)
     W = min(S, corr.CORR_CALIB_SPECTRA)
-    np.testing.assert_allclose(scales, oracle.scales_n(spec, W, W, qmax), rtol=1e-5)
+    np.testing.assert_allclose(scales, oracle.scales_n(spec, W, W, prec), rtol=1e-5)
     q_ref = quantise(oracle.track(spec, **m), scales)
     diff = q_gpu.astype(np.int32) - q_ref.astype(np.int32)
     assert np.max(np.abs(diff)) <= 1
