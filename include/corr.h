@@ -291,6 +291,40 @@ int corr_batch_read_cps(corr_handle b, int job, float *out);
 int corr_batch_read_cps_raw(corr_handle b, int job, double *out);
 int corr_batch_read_scales(corr_handle b, int job, float *out);
 
+/* --------------------------------------------------- no-allocation entry
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  One
+ * integration of n_spectra spectra, computed by the same kernels in the same
+ * order as corr_create + corr_set_precision + corr_process +
+ * corr_read_cps_raw, with no handle and no allocation: every buffer beyond
+ * the caller's input and outputs (records, partials, the float64 integration
+ * buffer, calibration sums, tickets, twiddle and region tables) lives in one
+ * static device array of 256 MiB per GPU, held until the process ends.  The
+ * integration runs in chunks of spectra cut to fit that array (for N = 44,
+ * K = 256: 2304 spectra in FP32, 9088 in INT8), so FP32 / FP16 results
+ * agree with corr_process within their tolerance and INT8 / INT16 sums are
+ * identical.
+ *   N, K, n_spectra, precision: as corr_create and corr_set_precision (INT8
+ *       also needs n_spectra <= 65536);
+ *   packed: DEVICE pointer, 16-byte aligned, frames as in corr_process;
+ *   cps: DEVICE pointer, 16-byte aligned, nb*K*2 doubles, overwritten with
+ *       the integration in corr_read_cps_raw's layout and units;
+ *   scales: INT8 / INT16: DEVICE pointer to N*K floats, written with the
+ *       integration's scales (as corr_read_scales) and read by the F-stage;
+ *       ignored (may be NULL) for FP32 / FP16;
+ *   stream: hipStream_t; everything is enqueued on it, nothing waits.
+ * The caller owns packed, cps and scales; they must stay valid until the
+ * stream passes this call.  CORR_EINVAL for a bad argument, or for a shape
+ * whose buffers do not fit the array even in chunks of 64 spectra (the
+ * message gives the bytes it would need; e.g. N = 256 at K = 512 needs a
+ * 269 MB integration buffer).  The first call on each device looks up the
+ * array and writes its twiddle tables with a synchronous copy, so it must
+ * not be captured; later calls only enqueue kernels.  Every call on one GPU
+ * uses that GPU's one array: calls that overlap on it (other streams,
+ * other threads) race and give wrong results.  */
+int corr_process_noalloc(int N, int K, int n_spectra, int precision, const void *packed, double *cps,
+                         float *scales, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

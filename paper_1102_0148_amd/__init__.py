@@ -37,7 +37,7 @@ EXPORTS = (
     "corr_spectra_bytes", "corr_process_spectra", "corr_debug_read_spectra", "corr_get_stats",
     "corr_enable_timing", "corr_destroy", "corr_last_error", "corr_batch_create",
     "corr_batch_set_tiles", "corr_batch_set_mode", "corr_batch_process", "corr_batch_read_cps",
-    "corr_batch_read_cps_raw", "corr_batch_read_scales",
+    "corr_batch_read_cps_raw", "corr_batch_read_scales", "corr_process_noalloc",
 )
 
 
@@ -110,6 +110,7 @@ def load(path: str = LIB_PATH):
         "corr_batch_read_cps": (I, [P, I, P]),
         "corr_batch_read_cps_raw": (I, [P, I, P]),
         "corr_batch_read_scales": (I, [P, I, P]),
+        "corr_process_noalloc": (I, [I, I, I, I, P, P, P, P]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -229,6 +230,12 @@ def corr_enable_timing(h, on: bool):
 def corr_destroy(h):
     if h:
         load().corr_destroy(h)
+
+
+def corr_process_noalloc(N: int, K: int, n_spectra: int, precision: int, packed_ptr: int, cps_ptr: int,
+                         scales_ptr: Optional[int] = None, stream: int = 0):
+    return _check(load().corr_process_noalloc(N, K, n_spectra, precision, packed_ptr, cps_ptr, scales_ptr,
+                                              stream))
 
 
 def corr_batch_create(jobs):

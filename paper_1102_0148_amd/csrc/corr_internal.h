@@ -119,6 +119,65 @@ struct XGroup {
     int kind[4];         // 1: diagonal region (upper triangle), 0: off-diagonal
 };
 
+// The regions of rb x rb antenna blocks that tile the triangle of nr region
+// rows: the nr diagonal regions first, then the off-diagonal ones row by row.
+__host__ __device__ inline int region_count(int nr) { return nr * (nr + 1) / 2; }
+__host__ __device__ inline int2 region_at(int idx, int nr, int rb) {
+    if (idx < nr) return make_int2(idx * rb, idx * rb);
+    idx -= nr;
+    for (int i = 0; i < nr; ++i) {
+        const int in_row = nr - 1 - i;
+        if (idx < in_row) return make_int2(i * rb, (i + 1 + idx) * rb);
+        idx -= in_row;
+    }
+    return make_int2(0, 0);
+}
+
+// Region groups sharing their blocks, for 4 x 4-block regions in an even
+// number nr of region rows: region rows 2i and 2i+1 give a diagonal group
+// (two diagonal regions and the off-diagonal one between them, 8 blocks) and,
+// with region columns 2j and 2j+1 (j > i), an off-diagonal group of four
+// regions (16 blocks).  Together they tile the triangle.  Listed per pair of
+// region rows: the diagonal group, then the off-diagonal ones.
+__host__ __device__ inline int group_count(int nr) { return (nr / 2) * (nr / 2 + 1) / 2; }
+__host__ __device__ inline XGroup group_at(int idx, int nr) {
+    XGroup g{};
+    const int h = nr / 2;
+    for (int ii = 0; ii < h; ++ii) {
+        const int in_row = h - ii;
+        if (idx >= in_row) {
+            idx -= in_row;
+            continue;
+        }
+        const int i = 2 * ii;
+        if (idx == 0) {
+            g.r0 = g.c0 = 4 * i;
+            g.diag = 1;
+            g.nreg = 3;
+            g.reg[0] = make_int2(4 * i, 4 * i);
+            g.kind[0] = 1;
+            g.reg[1] = make_int2(4 * i, 4 * i + 4);
+            g.kind[1] = 0;
+            g.reg[2] = make_int2(4 * i + 4, 4 * i + 4);
+            g.kind[2] = 1;
+        } else {
+            const int j = i + 2 * idx;
+            g.r0 = 4 * i;
+            g.c0 = 4 * j;
+            g.nreg = 4;
+            for (int k = 0; k < 4; ++k) {
+                g.reg[k] = make_int2(4 * i + 4 * (k / 2), 4 * j + 4 * (k % 2));
+                g.kind[k] = 0;
+            }
+        }
+        return g;
+    }
+    return g;
+}
+// Region groups are used for 4 x 4-block regions in an even number (>= 2) of
+// region rows.
+__host__ __device__ inline bool uses_groups(int rb, int nr) { return rb == 4 && nr >= 2 && nr % 2 == 0; }
+
 struct XArgs {
     const uint4 *spec;   // records, index rec_index(c, tq, a, K, a_pad)
     void *partial;       // [nsplit][K][nb] float2 (fp32/fp16) or int2 (int8)

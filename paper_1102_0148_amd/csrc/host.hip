@@ -13,6 +13,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -90,6 +91,16 @@ float2 twiddle(int64_t j, int64_t n) {
     double c, s;
     cos_sin_2pi(j, n, &c, &s);
     return make_float2((float)c, (float)-s);
+}
+
+// The F-stage's twiddle table for K channels: W_K^j, j < K, then W_2K^q,
+// q < K/2, then K bytes of zeros (the F-stage reads its absent blocks from
+// there).
+size_t tw_table_len(int K) { return (size_t)K + K / 2 + K / 8; }
+void fill_twiddles(float2 *tw, int K) {
+    for (size_t i = 0; i < tw_table_len(K); ++i) tw[i] = make_float2(0.0f, 0.0f);
+    for (int j = 0; j < K; ++j) tw[j] = twiddle(j, K);
+    for (int q = 0; q < K / 2; ++q) tw[K + q] = twiddle(q, 2 * K);
 }
 
 struct Timer {
@@ -215,19 +226,22 @@ int default_chunk(const corr_ctx *h) {
 
 int n_regions(const corr_ctx *h) { return h->n_diag + h->n_off; }
 
-int default_splits(const corr_ctx *h) {
-    const int64_t waves_per_split = (int64_t)n_regions(h) * h->K;
+// X-stage splits for chunks of `chunk` spectra: enough waves to fill the chip
+// (about 4096), and no partial summing more spectra than its form allows
+// (fp32 2048 and fp16 16384 for accuracy, int16 16384 for exact int32 digit
+// sums).
+int splits_for(int nregions, int K, int prec, int chunk) {
+    const int64_t waves_per_split = (int64_t)nregions * K;
     int s = (int)((4096 + waves_per_split - 1) / waves_per_split);
     s = std::max(1, std::min(64, s));
-    // spectra per partial: fp32 at most 2048 and fp16 16384 (accuracy), int16
-    // 16384 (exact int32 digit sums)
-    const int chunk = h->tiles.chunk_spectra;
-    const int cap = h->prec == kFP32 ? kF32SplitSpectra
-                  : h->prec == kFP16 ? kF16SplitSpectra
-                  : h->prec == kINT16 ? kI16SplitSpectra : 0;
+    const int cap = prec == kFP32 ? kF32SplitSpectra
+                  : prec == kFP16 ? kF16SplitSpectra
+                  : prec == kINT16 ? kI16SplitSpectra : 0;
     if (cap) s = std::max(s, std::min(64, (chunk + cap - 1) / cap));
     return s;
 }
+
+int default_splits(const corr_ctx *h) { return splits_for(n_regions(h), h->K, h->prec, h->tiles.chunk_spectra); }
 
 hipError_t set_regions(corr_ctx *h, int rb);
 
@@ -478,15 +492,14 @@ int descale_to_float(corr_ctx *h, const double *raw, float *out) {
     return CORR_OK;
 }
 
-// Tile the triangle of 16-antenna block pairs with regions of rb x rb blocks:
-// the diagonal regions first, then the off-diagonal ones.
+// Tile the triangle of 16-antenna block pairs with regions of rb x rb blocks
+// (region_at: the diagonal regions first, then the off-diagonal ones), and
+// for 4 x 4-block regions in an even number of region rows list the region
+// groups that share their blocks (group_at).
 hipError_t set_regions(corr_ctx *h, int rb) {
-    std::vector<int2> regs;
     const int nr = h->nblk / rb;
-    for (int i = 0; i < nr; ++i) regs.push_back(make_int2(i * rb, i * rb));
-    const int n_diag = (int)regs.size();
-    for (int i = 0; i < nr; ++i)
-        for (int j = i + 1; j < nr; ++j) regs.push_back(make_int2(i * rb, j * rb));
+    std::vector<int2> regs(region_count(nr));
+    for (int i = 0; i < (int)regs.size(); ++i) regs[i] = region_at(i, nr, rb);
     if (h->regions) hipFree(h->regions);
     h->regions = nullptr;
     hipError_t e = hipMalloc(&h->regions, regs.size() * sizeof(int2));
@@ -494,42 +507,14 @@ hipError_t set_regions(corr_ctx *h, int rb) {
     e = hipMemcpy(h->regions, regs.data(), regs.size() * sizeof(int2), hipMemcpyHostToDevice);
     if (e != hipSuccess) return e;
     h->rb = rb;
-    h->n_diag = n_diag;
-    h->n_off = (int)regs.size() - n_diag;
-    // Region groups sharing their blocks, for 4 x 4-block regions in an even
-    // number of region rows: region rows 2i and 2i+1 give a diagonal group
-    // (two diagonal regions and the off-diagonal one between them, 8 blocks)
-    // and, with region columns 2j and 2j+1 (j > i), an off-diagonal group of
-    // four regions (16 blocks).  Together they tile the triangle.
+    h->n_diag = nr;
+    h->n_off = (int)regs.size() - nr;
     if (h->xgroups) hipFree(h->xgroups);
     h->xgroups = nullptr;
     h->n_xgroups = 0;
-    if (rb == 4 && nr >= 2 && nr % 2 == 0) {
-        std::vector<XGroup> gs;
-        for (int i = 0; i < nr; i += 2) {
-            XGroup d{};
-            d.r0 = d.c0 = 4 * i;
-            d.diag = 1;
-            d.nreg = 3;
-            d.reg[0] = make_int2(4 * i, 4 * i);
-            d.kind[0] = 1;
-            d.reg[1] = make_int2(4 * i, 4 * i + 4);
-            d.kind[1] = 0;
-            d.reg[2] = make_int2(4 * i + 4, 4 * i + 4);
-            d.kind[2] = 1;
-            gs.push_back(d);
-            for (int j = i + 2; j < nr; j += 2) {
-                XGroup o{};
-                o.r0 = 4 * i;
-                o.c0 = 4 * j;
-                o.nreg = 4;
-                for (int k = 0; k < 4; ++k) {
-                    o.reg[k] = make_int2(4 * i + 4 * (k / 2), 4 * j + 4 * (k % 2));
-                    o.kind[k] = 0;
-                }
-                gs.push_back(o);
-            }
-        }
+    if (uses_groups(rb, nr)) {
+        std::vector<XGroup> gs(group_count(nr));
+        for (int i = 0; i < (int)gs.size(); ++i) gs[i] = group_at(i, nr);
         if ((e = hipMalloc(&h->xgroups, gs.size() * sizeof(XGroup))) != hipSuccess) return e;
         if ((e = hipMemcpy(h->xgroups, gs.data(), gs.size() * sizeof(XGroup), hipMemcpyHostToDevice)) != hipSuccess)
             return e;
@@ -566,11 +551,8 @@ corr_ctx *create_ctx(int N, int K, int S) {
     hipError_t e = hipGetDevice(&h->device);
     if (e != hipSuccess) return bail(e, "hipGetDevice");
     if ((e = set_regions(h, h->rb)) != hipSuccess) return bail(e, "regions");
-    // twiddles: W_K^j, j < K, then W_2K^q, q < K/2, then K bytes of zeros
-    // (the F-stage reads its absent blocks from there)
-    std::vector<float2> tw((size_t)K + K / 2 + K / 8, make_float2(0.0f, 0.0f));
-    for (int j = 0; j < K; ++j) tw[j] = twiddle(j, K);
-    for (int q = 0; q < K / 2; ++q) tw[K + q] = twiddle(q, 2 * K);
+    std::vector<float2> tw(tw_table_len(K));
+    fill_twiddles(tw.data(), K);
     if ((e = hipMalloc(&h->tw, tw.size() * sizeof(float2))) != hipSuccess) return bail(e, "hipMalloc(twiddles)");
     if ((e = hipMemcpy(h->tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess)
         return bail(e, "hipMemcpy(twiddles)");
@@ -1211,3 +1193,197 @@ int corr_batch_read_scales(corr_handle b, int job, float *out) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------- no-allocation entry point
+//
+// corr_process_noalloc runs one integration exactly as corr_process does
+// (same kernels, same calibration, the chunk cut to fit), with every buffer
+// beyond the caller's input and outputs in `scratch`, one static device array
+// per GPU that the library holds until the process ends.  Layout of the
+// array:
+//   [0, 32 KB)       twiddle tables of every channel count, each followed by
+//                    its zero page (written once per device at set-up)
+//   [32 KB, 33 KB)   F-stage tile tickets (cleared by every F-stage launch)
+//   [33 KB, ...)     saturation counter (only ever added to)
+//   [36 KB, 44 KB)   region table, [44 KB, 48 KB) region groups (per call)
+//   [64 KB, end)     per call: integration buffer, power partials (int8 /
+//                    int16), X-stage partials, spectra records + slack
+// Calls that overlap on one GPU share the array and race.
+
+namespace {
+
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+constexpr size_t kScrTicket = (size_t)32 << 10;
+constexpr size_t kScrSat = kScrTicket + kTicketBytes;
+constexpr size_t kScrRegions = (size_t)36 << 10;
+constexpr size_t kScrGroups = (size_t)44 << 10;
+constexpr size_t kScrHeader = (size_t)64 << 10;
+constexpr int kScrMaxDevices = 64;
+static_assert(kScrSat + 8 <= kScrRegions, "scratch header overlap");
+static_assert(kScrRegions + 528 * sizeof(int2) <= kScrGroups, "region table exceeds its slot");
+static_assert(kScrGroups + 10 * sizeof(XGroup) <= kScrHeader, "group table exceeds its slot");
+
+// Offset of the twiddle table of K channels: tables for K = 128, 256, ...
+// each rounded up to 256 bytes.
+size_t scr_tw_offset(int K) {
+    size_t off = 0;
+    for (int k = CORR_MIN_CHANNELS; k < K; k *= 2) off += round_up64(tw_table_len(k) * sizeof(float2), 256);
+    return off;
+}
+
+}  // namespace
+
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+namespace {
+
+std::mutex g_scr_mu;
+uint8_t *g_scr[kScrMaxDevices];  // the array's device address, per device
+
+// Once per device, with that device current: find the array's address (the
+// host-side name of a device variable is no device address) and write the
+// twiddle tables.  The copy is synchronous, so the first call on a device
+// must not be under stream capture.
+int scratch_setup(uint8_t **out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= kScrMaxDevices)
+        return fail(CORR_EINVAL, "device %d is beyond the %d the no-allocation entry point tracks", dev,
+                    kScrMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scr_mu);
+    if (!g_scr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        static float2 tw[kScrTicket / sizeof(float2)];
+        for (int K = CORR_MIN_CHANNELS; K <= CORR_MAX_CHANNELS; K *= 2)
+            fill_twiddles(tw + scr_tw_offset(K) / sizeof(float2), K);
+        HIP_TRY(hipMemcpy(p, tw, sizeof tw, hipMemcpyHostToDevice), "hipMemcpy(scratch twiddles)");
+        g_scr[dev] = static_cast<uint8_t *>(p);
+    }
+    *out = g_scr[dev];
+    return CORR_OK;
+}
+
+// The region table and region groups of one call, built on the device.
+__global__ __launch_bounds__(256) void noalloc_tables_kernel(int2 *regs, int nreg, XGroup *groups, int ngroups,
+                                                            int nr, int rb) {
+    for (int i = threadIdx.x; i < nreg; i += 256) regs[i] = region_at(i, nr, rb);
+    for (int i = threadIdx.x; i < ngroups; i += 256) groups[i] = group_at(i, nr);
+}
+
+// Scratch bytes for chunks of `chunk` spectra (the splits and record bytes
+// returned through the pointers).
+size_t noalloc_need(const corr_ctx &h, int chunk, size_t fixed, int *splits, size_t *spec_bytes) {
+    *splits = splits_for(n_regions(&h), h.K, h.prec, chunk);
+    const int ntq = round_up((chunk + h.TG - 1) / h.TG, kTQB);
+    *spec_bytes = (size_t)h.K * ntq * h.a_pad * kRecordBytes;
+    const size_t part = (size_t)*splits * h.K * h.nb * (h.prec == kINT16 ? 16 : 8);
+    return fixed + round_up64(part, 256) + *spec_bytes + kSpecSlack;
+}
+
+}  // namespace
+
+extern "C" int corr_process_noalloc(int N, int K, int n_spectra, int precision, const void *packed, double *cps,
+                                    float *scales, void *stream) {
+    g_err[0] = 0;
+    if (check_shape(N, K, n_spectra)) return CORR_EINVAL;
+    if (precision != CORR_FP32 && precision != CORR_FP16 && precision != CORR_INT8 && precision != CORR_INT16)
+        return fail(CORR_EINVAL, "unknown precision %d", precision);
+    if (precision == CORR_INT8 && n_spectra > 65536)
+        return fail(CORR_EINVAL, "INT8 needs n_spectra <= 65536 (exact int32 partials), got %d", n_spectra);
+    if (!packed || (reinterpret_cast<uintptr_t>(packed) & 15))
+        return fail(CORR_EINVAL, "packed_samples must be a 16-byte aligned device pointer");
+    if (!cps || (reinterpret_cast<uintptr_t>(cps) & 15))
+        return fail(CORR_EINVAL, "cps must be a 16-byte aligned device pointer");
+    if (is_quant(precision) && (!scales || (reinterpret_cast<uintptr_t>(scales) & 3)))
+        return fail(CORR_EINVAL, "INT8 / INT16 need a 4-byte aligned device pointer for the scales");
+    // the shape, regions and precision as corr_create / corr_set_precision /
+    // plan set them for a handle
+    corr_ctx h;
+    h.N = N;
+    h.K = K;
+    h.S = n_spectra;
+    h.prec = precision;
+    h.TG = record_times(precision);
+    h.nb = N * (N + 1) / 2;
+    h.nblk = (N + 15) / 16;
+    if (h.nblk <= 6) {
+        h.a_pad = 16 * h.nblk;
+        h.rb = h.nblk;
+    } else {
+        h.a_pad = round_up(N, 64);
+        h.nblk = h.a_pad / 16;
+        h.rb = 4;
+    }
+    if (precision == kINT16 && h.rb > 3) h.rb = h.nblk % 2 == 0 ? 2 : 1;
+    const int nr = h.nblk / h.rb;
+    h.n_diag = nr;
+    h.n_off = region_count(nr) - nr;
+    h.n_xgroups = uses_groups(h.rb, nr) ? group_count(nr) : 0;
+    // per-call buffers after the header: integration buffer, power partials,
+    // then X-stage partials and records for the largest chunk that fits
+    const size_t acc_bytes = (size_t)h.nb * K * sizeof(double2);
+    size_t power_bytes = 0;
+    if (is_quant(precision)) {
+        const int W = std::min(n_spectra, CORR_CALIB_SPECTRA);
+        const int nparts = ((W + 1) / 2 + kCalibTilesPerWG - 1) / kCalibTilesPerWG;
+        power_bytes = (size_t)nparts * h.a_pad * K * sizeof(float);
+    }
+    const size_t off_acc = kScrHeader;
+    const size_t off_power = off_acc + round_up64(acc_bytes, 256);
+    const size_t fixed = off_power + round_up64(power_bytes, 256);
+    int splits = 0;
+    size_t spec_bytes = 0;
+    const int64_t whole = round_up64(n_spectra, 64);
+    const size_t need64 = noalloc_need(h, 64, fixed, &splits, &spec_bytes);
+    if (need64 > kScratchBytes)
+        return fail(CORR_EINVAL,
+                    "N=%d K=%d precision %d needs %zu bytes of scratch even in chunks of 64 spectra; "
+                    "the no-allocation entry point has %zu", N, K, precision, need64, kScratchBytes);
+    int64_t lo = 1, hi = whole / 64;  // chunks of 64 lo spectra fit
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) / 2;
+        if (noalloc_need(h, (int)(mid * 64), fixed, &splits, &spec_bytes) <= kScratchBytes)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const int chunk = (int)(lo * 64);
+    noalloc_need(h, chunk, fixed, &splits, &spec_bytes);
+    const size_t off_part = fixed;
+    const size_t off_spec = off_part + round_up64((size_t)splits * K * h.nb * (precision == kINT16 ? 16 : 8), 256);
+
+    uint8_t *base = nullptr;
+    int rc = scratch_setup(&base);
+    if (rc) return rc;
+    h.device = 0;
+    h.tw = reinterpret_cast<float2 *>(base + scr_tw_offset(K));
+    h.fticket = reinterpret_cast<unsigned *>(base + kScrTicket);
+    h.sat = reinterpret_cast<unsigned long long *>(base + kScrSat);
+    h.regions = reinterpret_cast<int2 *>(base + kScrRegions);
+    h.xgroups = h.n_xgroups ? reinterpret_cast<XGroup *>(base + kScrGroups) : nullptr;
+    h.acc = reinterpret_cast<double2 *>(base + off_acc);
+    h.power = power_bytes ? reinterpret_cast<float *>(base + off_power) : nullptr;
+    h.scales = is_quant(precision) ? scales : nullptr;
+    h.partial = base + off_part;
+    h.spec = reinterpret_cast<uint4 *>(base + off_spec);
+    h.tiles.chunk_spectra = chunk;
+    h.tiles.x_splits = splits;
+    h.tiles.f_group = fstage_default_group(K, precision);
+    h.ntq_buf = round_up((chunk + h.TG - 1) / h.TG, kTQB);
+    h.spec_bytes = spec_bytes;
+    h.planned = h.started = true;
+    hipStream_t st = (hipStream_t)stream;
+    // Whatever the last call left: the tables of this shape, a cleared
+    // integration buffer, and records cleared so that padding antennas and
+    // padding spectra read as zeros.
+    hipLaunchKernelGGL(noalloc_tables_kernel, dim3(1), dim3(256), 0, st, h.regions, region_count(nr), h.xgroups,
+                       h.n_xgroups, nr, h.rb);
+    HIP_TRY(hipGetLastError(), "region table launch");
+    HIP_TRY(launch_fill_zero(h.acc, acc_bytes, st), "integration buffer clear");
+    HIP_TRY(launch_fill_zero(h.spec, spec_bytes, st), "records clear");
+    rc = process_one(&h, static_cast<const uint8_t *>(packed), st);
+    if (rc) return rc;
+    HIP_TRY(launch_finalize(h.acc, reinterpret_cast<double2 *>(cps), K, h.nb, st), "finalize launch");
+    return CORR_OK;
+}

@@ -113,3 +113,26 @@ def test_binding_constants_match_header():
     assert corr.CORR_MAX_ANTENNAS == int(re.search(r"#define CORR_MAX_ANTENNAS (\d+)", text).group(1))
     assert corr.CORR_MAX_CHANNELS == int(re.search(r"#define CORR_MAX_CHANNELS (\d+)", text).group(1))
 
+
+
+def test_noalloc_rejects_bad_arguments_before_any_hip_call(lib):
+    """The no-allocation entry point checks shape, precision, pointers and
+    its scratch budget on the host (no GPU here)."""
+    ok_ptr = 1 << 20                     # aligned, never dereferenced
+    cases = [
+        (1, 256, 16, corr.CORR_FP32, ok_ptr, ok_ptr, None),          # N too small
+        (44, 100, 16, corr.CORR_FP32, ok_ptr, ok_ptr, None),         # K not a power of two
+        (44, 256, 16, 9, ok_ptr, ok_ptr, None),                      # unknown precision
+        (44, 256, 70000, corr.CORR_INT8, ok_ptr, ok_ptr, ok_ptr),    # int8 over 65536 spectra
+        (44, 256, 16, corr.CORR_FP32, None, ok_ptr, None),           # no input
+        (44, 256, 16, corr.CORR_FP32, ok_ptr + 1, ok_ptr, None),     # misaligned input
+        (44, 256, 16, corr.CORR_FP32, ok_ptr, ok_ptr + 8, None),     # misaligned output
+        (44, 256, 16, corr.CORR_INT8, ok_ptr, ok_ptr, None),         # int8 without scales
+        (256, 512, 64, corr.CORR_FP32, ok_ptr, ok_ptr, None),        # does not fit the scratch
+        (512, 1024, 45, corr.CORR_INT16, ok_ptr, ok_ptr, ok_ptr),    # does not fit the scratch
+    ]
+    for args in cases:
+        assert lib.corr_process_noalloc(*args, None) == corr.CORR_EINVAL, args
+        assert corr.corr_last_error()
+    lib.corr_process_noalloc(256, 512, 64, corr.CORR_FP32, ok_ptr, ok_ptr, None, None)
+    assert "bytes of scratch" in corr.corr_last_error()
