@@ -101,6 +101,33 @@ typedef struct {
 int corr_set_tiles(corr_handle h, const corr_tiles *t);
 int corr_get_tiles(corr_handle h, corr_tiles *t);
 
+/* How corr_process runs an integration (Section 4 leaves moving the FFT and
+ * the timeslice grouping ahead of the cross-multiplier as future work; the
+ * fused pipeline is that, on one GPU):
+ *   CORR_PIPELINE_STAGED (default): per chunk of chunk_spectra spectra an
+ *     F-stage launch writes the chunk's records, an X-stage launch reads them
+ *     into partials and a dump adds those into float64.
+ *   CORR_PIPELINE_FUSED: one persistent kernel per integration (launched
+ *     cooperatively: all its workgroups resident).  Some workgroups transform
+ *     chunks of chunk_spectra spectra into a ring of ring_slots record
+ *     buffers small enough to stay in the caches; the others are X workers
+ *     whose accumulators stay in registers across all chunks and are written
+ *     out once (float forms: every 2048 (FP32) / 16384 (FP16) spectra of a
+ *     partial); one dump follows.  f_workgroups_per_cu: workgroups per CU that
+ *     run the F-stage (the rest of the CU's resident workgroups run X).
+ *     FP32, FP16 and INT8 with N <= 48; no delay / phase tracking; not in
+ *     batches.  Results: INT8 identical to the staged pipeline, FP32 / FP16
+ *     within their tolerance.
+ * 0 for chunk_spectra (a multiple of 64), ring_slots (1..8) or
+ * f_workgroups_per_cu picks a default.  Before the first process call only
+ * (CORR_ESTATE after); a shape or precision the fused kernel does not cover
+ * fails the first process call (and corr_get_tiles) with CORR_EINVAL.  With
+ * FUSED, corr_get_tiles reports chunk_spectra, the partials per channel in
+ * x_splits and the F group.  */
+#define CORR_PIPELINE_STAGED 0
+#define CORR_PIPELINE_FUSED 1
+int corr_set_pipeline(corr_handle h, int pipeline, int chunk_spectra, int ring_slots, int f_workgroups_per_cu);
+
 /* Correlate one integration.  packed_samples: DEVICE pointer to
  * n_spectra*N*K bytes in the frame layout above.  Enqueues the whole F + X +
  * dump sequence on `stream` and returns without waiting; the result is added
@@ -237,6 +264,8 @@ typedef struct {
     int chunk_spectra, x_splits, f_group;
     double ms_calib, ms_f, ms_x, ms_dump; /* 0 unless timing is on */
     int64_t launches_f, launches_x;
+    double ms_fused;                      /* fused pipeline: the F + X kernel */
+    int64_t launches_fused;
 } corr_stats;
 int corr_get_stats(corr_handle h, corr_stats *out);
 /* on != 0: record HIP events around each stage (adds a little launch work). */

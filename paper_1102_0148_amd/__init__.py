@@ -27,6 +27,8 @@ CORR_CALIB_SPECTRA = 1024
 CORR_MAX_ANTENNAS, CORR_MAX_CHANNELS = 512, 1024
 PRECISIONS = {"fp32": CORR_FP32, "fp16": CORR_FP16, "int8": CORR_INT8, "int16": CORR_INT16}
 CORR_BATCH_BRANCHES, CORR_BATCH_PERSISTENT = 0, 1
+CORR_PIPELINE_STAGED, CORR_PIPELINE_FUSED = 0, 1
+PIPELINES = {"staged": CORR_PIPELINE_STAGED, "fused": CORR_PIPELINE_FUSED}
 BATCH_MODES = {"branches": CORR_BATCH_BRANCHES, "persistent": CORR_BATCH_PERSISTENT}
 
 # Every symbol include/corr.h declares.
@@ -37,7 +39,7 @@ EXPORTS = (
     "corr_spectra_bytes", "corr_process_spectra", "corr_debug_read_spectra", "corr_get_stats",
     "corr_enable_timing", "corr_destroy", "corr_last_error", "corr_batch_create",
     "corr_batch_set_tiles", "corr_batch_set_mode", "corr_batch_process", "corr_batch_read_cps",
-    "corr_batch_read_cps_raw", "corr_batch_read_scales", "corr_process_noalloc",
+    "corr_batch_read_cps_raw", "corr_batch_read_scales", "corr_process_noalloc", "corr_set_pipeline",
 )
 
 
@@ -57,7 +59,8 @@ class corr_stats(ctypes.Structure):
                 ("x_splits", ctypes.c_int), ("f_group", ctypes.c_int),
                 ("ms_calib", ctypes.c_double), ("ms_f", ctypes.c_double),
                 ("ms_x", ctypes.c_double), ("ms_dump", ctypes.c_double),
-                ("launches_f", ctypes.c_int64), ("launches_x", ctypes.c_int64)]
+                ("launches_f", ctypes.c_int64), ("launches_x", ctypes.c_int64),
+                ("ms_fused", ctypes.c_double), ("launches_fused", ctypes.c_int64)]
 
 
 class corr_ingest_stats(ctypes.Structure):
@@ -111,6 +114,7 @@ def load(path: str = LIB_PATH):
         "corr_batch_read_cps_raw": (I, [P, I, P]),
         "corr_batch_read_scales": (I, [P, I, P]),
         "corr_process_noalloc": (I, [I, I, I, I, P, P, P, P]),
+        "corr_set_pipeline": (I, [P, I, I, I, I]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -181,6 +185,10 @@ def corr_get_tiles(h) -> dict:
     t = corr_tiles()
     _check(load().corr_get_tiles(h, ctypes.byref(t)))
     return {"chunk_spectra": t.chunk_spectra, "x_splits": t.x_splits, "f_group": t.f_group}
+
+
+def corr_set_pipeline(h, pipeline: int, chunk_spectra: int = 0, ring_slots: int = 0, f_workgroups_per_cu: int = 0):
+    return _check(load().corr_set_pipeline(h, pipeline, chunk_spectra, ring_slots, f_workgroups_per_cu))
 
 
 def corr_process(h, packed_ptr: int, stream: int = 0):
@@ -289,9 +297,12 @@ def n_baselines(N: int) -> int:
 class Correlator:
     """One correlation (N antennas, K channels, n_spectra per integration)."""
 
-    def __init__(self, N: int, K: int, n_spectra: int, precision="fp32", tiles=None):
+    def __init__(self, N: int, K: int, n_spectra: int, precision="fp32", tiles=None, pipeline=None):
         """tiles: None (library defaults), "auto" (the autotuner's table,
-        defaults where it has no entry) or a dict of corr_tiles fields."""
+        defaults where it has no entry) or a dict of corr_tiles fields.
+        pipeline: None / "staged", or "fused" optionally with its parameters
+        as a dict {"chunk_spectra", "ring_slots", "f_workgroups_per_cu"}
+        (with tiles="auto", the autotuner's fused entry when it has one)."""
         self.N, self.K, self.S = N, K, n_spectra
         self.nb = n_baselines(N)
         self.h = corr_create(N, K, n_spectra)
@@ -299,9 +310,21 @@ class Correlator:
             mode = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
             corr_set_precision(self.h, mode)
             self.precision = mode
+            name = {v: k for k, v in PRECISIONS.items()}[mode]
+            fused = pipeline == "fused" or isinstance(pipeline, dict)
+            if fused:
+                params = dict(pipeline) if isinstance(pipeline, dict) else {}
+                if not params and isinstance(tiles, str) and tiles == "auto":
+                    from . import tune
+                    found = tune.lookup(N, K, n_spectra, name, mode="fused")
+                    params = {k: found[k] for k in ("chunk_spectra", "ring_slots", "f_workgroups_per_cu")} \
+                        if found else {}
+                corr_set_pipeline(self.h, CORR_PIPELINE_FUSED, **params)
+                tiles = None
+            elif pipeline not in (None, "staged"):
+                raise ValueError(f"unknown pipeline {pipeline!r}")
             if isinstance(tiles, str) and tiles == "auto":
                 from . import tune
-                name = {v: k for k, v in PRECISIONS.items()}[mode]
                 found = tune.lookup(N, K, n_spectra, name)
                 tiles = {k: found[k] for k in ("chunk_spectra", "x_splits", "f_group")} if found else None
             if tiles:

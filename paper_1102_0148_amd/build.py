@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libcorr.so")
-SOURCES = ["host.hip", "fstage.hip", "xstage.hip", "dump.hip", "batch.hip", "ingest.hip"]
+SOURCES = ["host.hip", "fstage.hip", "xstage.hip", "dump.hip", "batch.hip", "ingest.hip", "fused.hip"]
 ARCH = "gfx950"
 # Packed fp32 VALU forms are kept out of every kernel on this target, and
 # floating-point contraction is off: fused multiply-adds are written out.

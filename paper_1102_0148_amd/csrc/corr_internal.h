@@ -201,6 +201,50 @@ hipError_t launch_xgroups(int prec, const XArgs &a, hipStream_t st);
 // the diagonal; a.nkb even; partials are double2 (exact integers).
 hipError_t launch_xstage16(int rb, int kind, const XArgs &a, hipStream_t st);
 
+// ---------------------------------------------------------------- fused F -> X
+// One persistent kernel, launched cooperatively (every workgroup resident):
+// workgroups [0, n_fwg) run the F-stage chunk by chunk into a ring of record
+// slots, the others are X workers whose four waves each own one (channel,
+// split) unit and keep its accumulators in registers across the chunks.  A
+// chunk's records are read while they are still in the caches, and the
+// X-stage's prologue, epilogue and partial writes are paid once per
+// integration (or once per flush, for the float forms' accuracy) instead of
+// once per chunk.  Single-region shapes only (at most 6 antenna blocks).
+struct FxArgs {
+    FArgs f;             // in: the whole integration; spec: the ring's first slot
+    XArgs x;             // partial, N, a_pad, K, nb; nsplit = splits per channel
+    unsigned *ctr;       // counters (layout below), zero at launch
+    unsigned *err;       // set when a wait gives up (sticky: not cleared per launch)
+    int S;               // spectra in the integration
+    int chunk;           // spectra per chunk (a multiple of 64)
+    int nchunks;
+    int ring;            // slots in the ring
+    int64_t slot_recs;   // records (uint4) per slot
+    int n_fwg;           // workgroups [0, n_fwg) run the F-stage
+    int flush_chunks;    // X units start a new partial every this many chunks
+};
+// Counter words: per chunk c from kFxHdr + c kFxPerChunk: the eight per-XCD
+// tile tickets, the eight per-XCD counts of F workgroups that finished the
+// chunk (kTicketStride apart), then `done` (XCDs whose F workgroups all
+// finished it and whose L2 has been written back) and `consumed` (X
+// workgroups that finished it), each on a 128-byte line of its own.
+constexpr int kFxHdr = 32;
+constexpr int kFxXcdDone = 8 * kTicketStride;
+constexpr int kFxDone = kFxXcdDone + 8 * kTicketStride;
+constexpr int kFxConsumed = kFxDone + 32;
+constexpr int kFxPerChunk = kFxConsumed + 32;
+// Register sets of an X worker's prefetch ring (a fused X wave runs alone on
+// its SIMD, so it keeps three k-blocks in flight).
+constexpr int kFxXBuf = 4;
+// Largest region side (in 16-antenna blocks) the fused kernel is built for.
+constexpr int kFxMaxRB = 3;
+// The chunk's spin limit is the batch kernel's (about a second).
+hipError_t launch_fused(int M, int prec, int rb, const FxArgs &a, int grid, hipStream_t st);
+// Workgroups of the fused kernel that stay resident per CU (0 if the
+// combination is not built), and its F group.
+int fused_blocks_per_cu(int M, int prec, int rb);
+int fused_group(int M, int prec);
+
 // ---------------------------------------------------------------- dump etc.
 // acc[f][bl] (double2) += sum over splits of partial[sp][f][bl], in split order.
 hipError_t launch_dump(int prec, const void *partial, double2 *acc, int nsplit, int K, int nb,

@@ -152,13 +152,25 @@ struct corr_ctx {
     unsigned *ingest_ctr = nullptr;
     hipStream_t ingest_stream = nullptr;
     bool ingested = false, ingest_pending = false;
+    // fused pipeline: requested chunk, ring and F workgroups per CU (0 =
+    // default), then the plan: grid, F workgroups, splits per channel, flush
+    // period, chunks, partial slots, records per ring slot; counters and the
+    // sticky error flag
+    int pipeline = CORR_PIPELINE_STAGED;
+    int fx_chunk = 0, fx_ring = 0, fx_fpc = 0;
+    int fx_grid = 0, fx_nfwg = 0, fx_nsplit = 0, fx_flush = 0, fx_nchunks = 0, fx_nslots = 0;
+    int64_t fx_slot_recs = 0;
+    unsigned *fx_ctr = nullptr;
+    size_t fx_ctr_bytes = 0;
+    unsigned *fx_err = nullptr;
+    const uint4 *dbg_spec = nullptr;  // records of the last chunk (fused: its ring slot)
     // state
     int64_t accumulated = 0;
     int last_chunk = 0;
     hipStream_t last_stream = nullptr;
     bool timing = false;
-    double ms[4] = {0, 0, 0, 0};  // calib, F, X, dump
-    int64_t launches_f = 0, launches_x = 0;
+    double ms[5] = {0, 0, 0, 0, 0};  // calib, F, X, dump, fused F + X
+    int64_t launches_f = 0, launches_x = 0, launches_fused = 0;
     std::vector<Timer> timers;
     // batch: the jobs, their device descriptors, the work list, counters
     // (ticket, error flag, then kBatchCounters per job) and the captured graph
@@ -206,7 +218,8 @@ void free_ctx(corr_ctx *h) {
     for (hipEvent_t e : h->br_events) hipEventDestroy(e);
     void *bufs[] = {h->spec,    h->partial, h->acc,     h->stage,   h->tw,     h->scales,
                     h->power,   h->regions, h->sat,     h->fticket, h->xgroups, h->bjobs,
-                    h->in_ptrs, h->items,   h->bctr,    h->track,   h->ingest_owner, h->ingest_ctr};
+                    h->in_ptrs, h->items,   h->bctr,    h->track,   h->ingest_owner, h->ingest_ctr,
+                    h->fx_ctr,  h->fx_err};
     for (void *p : bufs)
         if (p) hipFree(p);
     for (corr_ctx *j : h->jobs) free_ctx(j);
@@ -246,10 +259,84 @@ int default_splits(const corr_ctx *h) { return splits_for(n_regions(h), h->K, h-
 hipError_t set_regions(corr_ctx *h, int rb);
 
 // Resolve tiles and allocate the precision-dependent scratch.
+// The fused pipeline's plan: roles, splits, chunks, ring and partials.
+int plan_fused(corr_ctx *h) {
+    if (h->prec != kFP32 && h->prec != kFP16 && h->prec != kINT8)
+        return fail(CORR_EINVAL, "the fused pipeline runs FP32, FP16 and INT8 only");
+    if (h->n_diag != 1 || h->n_off != 0 || h->rb > kFxMaxRB)
+        return fail(CORR_EINVAL, "the fused pipeline covers N <= %d (one region of at most %d antenna blocks), got N=%d",
+                    16 * kFxMaxRB, kFxMaxRB, h->N);
+    const int per_cu = fused_blocks_per_cu(h->K, h->prec, h->rb);
+    int cus = 0;
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device), "hipDeviceGetAttribute");
+    if (per_cu < 2 || cus < 1) return fail(CORR_EINVAL, "the fused kernel keeps %d workgroups per CU resident; it needs 2", per_cu);
+    // workgroup b runs on XCD b mod 8 (gfx950: 8 XCDs of 32 CUs), and each
+    // XCD's F workgroups publish through that XCD's L2
+    if (cus % 8) return fail(CORR_EINVAL, "the fused pipeline expects the CUs in 8 XCDs (%d CUs)", cus);
+    const int fpc = h->fx_fpc ? h->fx_fpc : per_cu - 1;
+    if (fpc < 1 || fpc >= per_cu)
+        return fail(CORR_EINVAL, "f_workgroups_per_cu=%d out of [1, %d] (%d workgroups per CU)", fpc, per_cu - 1, per_cu);
+    h->fx_grid = per_cu * cus;
+    h->fx_nfwg = fpc * cus;
+    const int x_waves = 4 * (per_cu - fpc) * cus;
+    h->fx_nsplit = std::max(1, std::min(64, x_waves / h->K));
+    if (h->K > x_waves) return fail(CORR_EINVAL, "the fused pipeline needs %d X waves for K=%d, has %d", h->K, h->K, x_waves);
+    // chunks: records of a slot about 48 MB, so a ring of three stays in the
+    // 256 MB Infinity Cache
+    const int64_t per_spectrum = (int64_t)h->a_pad * h->K * (kRecordBytes / h->TG);
+    int chunk = h->fx_chunk;
+    if (!chunk) chunk = (int)std::max<int64_t>(64, ((int64_t)48 << 20) / per_spectrum / 64 * 64);
+    chunk = (int)std::min<int64_t>(chunk, round_up64(h->S, 64));
+    h->fx_nchunks = (h->S + chunk - 1) / chunk;
+    h->fx_ring = std::max(1, std::min(h->fx_ring ? h->fx_ring : 3, h->fx_nchunks));
+    const int ntq_slot = round_up((chunk + h->TG - 1) / h->TG, kTQB);
+    h->fx_slot_recs = (int64_t)h->K * ntq_slot * h->a_pad;
+    // a partial sums at most 2048 (fp32) / 16384 (fp16) spectra; int8 sums
+    // are exact over the whole integration
+    const int kb_chunk = (chunk + 4 * h->TG - 1) / (4 * h->TG);
+    const int per_unit = (kb_chunk + h->fx_nsplit - 1) / h->fx_nsplit * 4 * h->TG;
+    const int cap = h->prec == kFP32 ? kF32SplitSpectra : h->prec == kFP16 ? kF16SplitSpectra : 0;
+    h->fx_flush = cap ? std::max(1, cap / per_unit) : h->fx_nchunks;
+    if (cap && per_unit > cap)
+        return fail(CORR_EINVAL, "chunk_spectra=%d gives %d spectra per partial in one chunk, above %d", chunk, per_unit, cap);
+    const int epochs = (h->fx_nchunks + h->fx_flush - 1) / h->fx_flush;
+    h->fx_nslots = epochs * h->fx_nsplit;
+    h->tiles.chunk_spectra = chunk;
+    h->tiles.x_splits = h->fx_nslots;
+    h->tiles.f_group = fused_group(h->K, h->prec);
+    h->ntq_buf = ntq_slot;
+    h->spec_bytes = (size_t)h->fx_ring * h->fx_slot_recs * kRecordBytes;
+    HIP_TRY(hipMalloc(&h->spec, h->spec_bytes + kSpecSlack), "hipMalloc(record ring)");
+    HIP_TRY(hipMemset(h->spec, 0, h->spec_bytes + kSpecSlack), "hipMemset(record ring)");
+    HIP_TRY(hipMalloc(&h->partial, (size_t)h->fx_nslots * h->K * h->nb * 8), "hipMalloc(partials)");
+    h->fx_ctr_bytes = (size_t)round_up((kFxHdr + h->fx_nchunks * kFxPerChunk) * (int)sizeof(unsigned), 16);
+    HIP_TRY(hipMalloc(&h->fx_ctr, h->fx_ctr_bytes), "hipMalloc(fused counters)");
+    HIP_TRY(hipMalloc(&h->fx_err, 16), "hipMalloc(fused error flag)");
+    HIP_TRY(hipMemset(h->fx_err, 0, 16), "hipMemset(fused error flag)");
+    return CORR_OK;
+}
+
+int alloc_calibration(corr_ctx *h) {
+    if (!is_quant(h->prec)) return CORR_OK;
+    const int W = std::min(h->S, CORR_CALIB_SPECTRA);
+    const int ntq_w = (W + 1) / 2;
+    const int nparts = (ntq_w + kCalibTilesPerWG - 1) / kCalibTilesPerWG;
+    HIP_TRY(hipMalloc(&h->scales, (size_t)h->N * h->K * sizeof(float)), "hipMalloc(scales)");
+    HIP_TRY(hipMalloc(&h->power, (size_t)nparts * h->a_pad * h->K * sizeof(float)), "hipMalloc(power)");
+    return CORR_OK;
+}
+
 int plan(corr_ctx *h) {
     if (h->planned) return CORR_OK;
     HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
     h->TG = record_times(h->prec);
+    if (h->pipeline == CORR_PIPELINE_FUSED) {
+        int rc = plan_fused(h);
+        if (!rc) rc = alloc_calibration(h);
+        if (rc) return rc;
+        h->planned = true;
+        return CORR_OK;
+    }
     if (h->tiles.chunk_spectra == 0) h->tiles.chunk_spectra = default_chunk(h);
     if (h->tiles.f_group == 0) h->tiles.f_group = fstage_default_group(h->K, h->prec);
     if (h->tiles.x_splits == 0) h->tiles.x_splits = default_splits(h);
@@ -276,13 +363,8 @@ int plan(corr_ctx *h) {
     HIP_TRY(hipMemset(h->spec, 0, h->spec_bytes + kSpecSlack), "hipMemset(spectra chunk)");
     HIP_TRY(hipMalloc(&h->partial, (size_t)h->tiles.x_splits * h->K * h->nb * (h->prec == kINT16 ? 16 : 8)),
             "hipMalloc(partials)");
-    if (is_quant(h->prec)) {
-        const int W = std::min(h->S, CORR_CALIB_SPECTRA);
-        const int ntq_w = (W + 1) / 2;
-        const int nparts = (ntq_w + kCalibTilesPerWG - 1) / kCalibTilesPerWG;
-        HIP_TRY(hipMalloc(&h->scales, (size_t)h->N * h->K * sizeof(float)), "hipMalloc(scales)");
-        HIP_TRY(hipMalloc(&h->power, (size_t)nparts * h->a_pad * h->K * sizeof(float)), "hipMalloc(power)");
-    }
+    int rc = alloc_calibration(h);
+    if (rc) return rc;
     h->planned = true;
     return CORR_OK;
 }
@@ -419,6 +501,47 @@ int process_one(corr_ctx *h, const uint8_t *in, hipStream_t st) {
                 "hipMemcpyAsync(tracking)");
         h->track_dirty = false;
     }
+    if (h->pipeline == CORR_PIPELINE_FUSED) {
+        if (h->track_on) return fail(CORR_EINVAL, "the fused pipeline does not apply delay / phase tracking");
+        if (h->in_slot) return fail(CORR_EINVAL, "the fused pipeline does not run in batches");
+        FxArgs fx{};
+        fx.f.in = in;
+        fx.f.spec = h->spec;
+        fx.f.scales = h->scales;
+        fx.f.tw = h->tw;
+        fx.f.sat = h->sat;
+        fx.f.N = h->N;
+        fx.f.a_pad = h->a_pad;
+        fx.f.ntq = h->ntq_buf;
+        fx.f.ngroups = (h->N + h->tiles.f_group - 1) / h->tiles.f_group;
+        fx.x.partial = h->partial;
+        fx.x.N = h->N;
+        fx.x.a_pad = h->a_pad;
+        fx.x.K = h->K;
+        fx.x.nb = h->nb;
+        fx.x.nsplit = h->fx_nsplit;
+        fx.ctr = h->fx_ctr;
+        fx.err = h->fx_err;
+        fx.S = h->S;
+        fx.chunk = chunk;
+        fx.nchunks = h->fx_nchunks;
+        fx.ring = h->fx_ring;
+        fx.slot_recs = h->fx_slot_recs;
+        fx.n_fwg = h->fx_nfwg;
+        fx.flush_chunks = h->fx_flush;
+        HIP_TRY(launch_fill_zero(h->fx_ctr, h->fx_ctr_bytes, st), "fused counter clear");
+        timer_begin(h, 4, st);
+        HIP_TRY(launch_fused(h->K, h->prec, h->rb, fx, h->fx_grid, st), "fused F + X launch");
+        timer_end(h, st);
+        h->launches_fused++;
+        timer_begin(h, 3, st);
+        HIP_TRY(launch_dump(h->prec, h->partial, h->acc, h->fx_nslots, h->K, h->nb, st), "dump launch");
+        timer_end(h, st);
+        const int last = h->fx_nchunks - 1;
+        h->last_chunk = h->S - last * chunk;
+        h->dbg_spec = h->spec + (int64_t)(last % h->fx_ring) * h->fx_slot_recs;
+        return CORR_OK;
+    }
     for (int c0 = 0; c0 < h->S; c0 += chunk) {
         const int Sc = std::min(chunk, h->S - c0);
         // whole k-blocks; int16 steps take two k-blocks
@@ -447,6 +570,7 @@ int process_one(corr_ctx *h, const uint8_t *in, hipStream_t st) {
         int rc = launch_x_and_dump(h, h->spec, h->ntq_buf, ntq_used / 4, st);
         if (rc) return rc;
         h->last_chunk = Sc;
+        h->dbg_spec = h->spec;
     }
     return CORR_OK;
 }
@@ -467,6 +591,14 @@ int read_raw_into(corr_ctx *h, double *out) {
     if (rc) return rc;
     HIP_TRY(hipGetLastError(), "asynchronous error");
     h->accumulated = 0;
+    if (h->fx_err) {
+        unsigned err = 0;
+        HIP_TRY(hipMemcpy(&err, h->fx_err, sizeof err, hipMemcpyDeviceToHost), "hipMemcpy(fused error flag)");
+        if (err) {
+            HIP_TRY(hipMemset(h->fx_err, 0, sizeof err), "hipMemset(fused error flag)");
+            return fail(CORR_EHIP, "fused pipeline: a wait between workgroups exceeded its limit; results are invalid");
+        }
+    }
     return CORR_OK;
 }
 
@@ -607,6 +739,24 @@ int corr_get_tiles(corr_handle hh, corr_tiles *t) {
     int rc = plan(h);
     if (rc) return rc;
     *t = h->tiles;
+    return CORR_OK;
+}
+
+int corr_set_pipeline(corr_handle hh, int pipeline, int chunk_spectra, int ring_slots, int f_workgroups_per_cu) {
+    corr_ctx *h = single(hh);
+    if (!h) return fail(CORR_EINVAL, "invalid handle");
+    if (pipeline != CORR_PIPELINE_STAGED && pipeline != CORR_PIPELINE_FUSED)
+        return fail(CORR_EINVAL, "pipeline %d is neither CORR_PIPELINE_STAGED nor CORR_PIPELINE_FUSED", pipeline);
+    if (chunk_spectra < 0 || chunk_spectra % 64)
+        return fail(CORR_EINVAL, "chunk_spectra=%d must be a non-negative multiple of 64", chunk_spectra);
+    if (ring_slots < 0 || ring_slots > 8) return fail(CORR_EINVAL, "ring_slots=%d out of [0, 8]", ring_slots);
+    if (f_workgroups_per_cu < 0 || f_workgroups_per_cu > 16)
+        return fail(CORR_EINVAL, "f_workgroups_per_cu=%d out of [0, 16]", f_workgroups_per_cu);
+    if (h->started || h->planned) return fail(CORR_ESTATE, "the pipeline is fixed once processing has started");
+    h->pipeline = pipeline;
+    h->fx_chunk = chunk_spectra;
+    h->fx_ring = ring_slots;
+    h->fx_fpc = f_workgroups_per_cu;
     return CORR_OK;
 }
 
@@ -785,7 +935,7 @@ int corr_debug_read_spectra(corr_handle hh, void *out, int *n_spectra) {
     HIP_TRY(hipStreamSynchronize(h->last_stream), "hipStreamSynchronize");
     // time blocks are outermost, so the chunk's records are a prefix
     const size_t bytes = corr_spectra_bytes(hh, h->last_chunk);
-    HIP_TRY(hipMemcpy(out, h->spec, bytes, hipMemcpyDeviceToHost), "hipMemcpy(spectra)");
+    HIP_TRY(hipMemcpy(out, h->dbg_spec ? h->dbg_spec : h->spec, bytes, hipMemcpyDeviceToHost), "hipMemcpy(spectra)");
     return CORR_OK;
 }
 
@@ -812,6 +962,8 @@ int corr_get_stats(corr_handle hh, corr_stats *out) {
     out->ms_dump = h->ms[3];
     out->launches_f = h->launches_f;
     out->launches_x = h->launches_x;
+    out->ms_fused = h->ms[4];
+    out->launches_fused = h->launches_fused;
     return CORR_OK;
 }
 
@@ -822,7 +974,7 @@ int corr_enable_timing(corr_handle hh, int on) {
     if (rc) return rc;
     h->timing = on != 0;
     for (double &m : h->ms) m = 0.0;
-    h->launches_f = h->launches_x = 0;
+    h->launches_f = h->launches_x = h->launches_fused = 0;
     return CORR_OK;
 }
 

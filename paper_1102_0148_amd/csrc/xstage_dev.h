@@ -83,14 +83,184 @@ __device__ __forceinline__ f32x4 mf32(float a, float b, f32x4 acc) {
 }
 
 
+// The accumulators of one wavefront's region: RB x RB pairs of 16-antenna
+// blocks (DIAG: the upper triangle of a diagonal region) of one channel, both
+// 16x16 accumulators of every pair in registers.  zero() clears them, run()
+// adds a range of k-blocks of a record buffer laid out as rec_index, store()
+// turns them into (Re, Im) and writes the pairs a <= b < N of a partial row.
+template <int PREC, int RB, bool DIAG>
+struct XRegion {
+    typedef typename AccT<PREC>::type acc_t;
+    static constexpr bool F3M = PREC == kFP32;  // three-product form
+    // Q form: accR = Re, accI = Im.  fp32: diagonal pair accR = Re, accI = M;
+    // off-diagonal pair accR = P1, accI = P2, acc3 = P3.
+    acc_t accR[RB][RB], accI[RB][RB], acc3[RB][RB];
+
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int I = 0; I < RB; ++I)
+#pragma unroll
+            for (int J = 0; J < RB; ++J) {
+                accR[I][J] = acc_t{0, 0, 0, 0};
+                accI[I][J] = acc_t{0, 0, 0, 0};
+                acc3[I][J] = acc_t{0, 0, 0, 0};
+            }
+    }
+
+    // k-blocks [kb0, kb1) of channel f, row blocks I0.., column blocks J0..
+    // NBUF register sets rotate: the records of the next NBUF - 1 k-blocks are
+    // in flight while one is multiplied (2 where many waves share a SIMD and
+    // hide each other's latency; more for a wave that runs alone).
+    template <int NBUF = 2>
+    __device__ __forceinline__ void run(const uint4 *spec, int K, int a_pad, int f, int I0, int J0, int kb0,
+                                        int kb1) {
+        const int lane = threadIdx.x & 63;
+        // lane (row r, group g) reads record tq = 4 kb + g of antenna 16 I + r;
+        // a k-block is the (kb mod 4)-th quarter of time block kb / 4
+        const uint4 *base = spec + (int64_t)f * kTQB * a_pad + (lane >> 4) * a_pad + (lane & 15);
+        const int64_t bstride = (int64_t)K * kTQB * a_pad;
+
+        // two register sets alternate: the records of the next k-block are in
+        // flight while the current one is multiplied
+        auto load = [&](int kb, uint4 *r, uint4 *c) {
+            const uint4 *rec = base + (kb >> 2) * bstride + (kb & 3) * 4 * a_pad;
+#pragma unroll
+            for (int I = 0; I < RB; ++I) r[I] = rec[(I0 + I) * 16];
+            if constexpr (!DIAG) {
+#pragma unroll
+                for (int J = 0; J < RB; ++J) c[J] = rec[(J0 + J) * 16];
+            }
+        };
+        auto compute = [&](const uint4 *pr, const uint4 *pc) {
+            if constexpr (F3M) {
+                // record = (re t0, re t1, im t0, im t1)
+                float sr[RB][2], dc[RB][2];
+#pragma unroll
+                for (int I = 0; I < RB; ++I) {
+                    const float4 p = *reinterpret_cast<const float4 *>(&pr[I]);
+                    sr[I][0] = p.x + p.z;
+                    sr[I][1] = p.y + p.w;
+                }
+#pragma unroll
+                for (int J = 0; J < RB; ++J) {
+                    const float4 p = *reinterpret_cast<const float4 *>(DIAG ? &pr[J] : &pc[J]);
+                    dc[J][0] = p.x - p.z;
+                    dc[J][1] = p.y - p.w;
+                }
+#pragma unroll
+                for (int I = 0; I < RB; ++I)
+#pragma unroll
+                    for (int J = 0; J < RB; ++J) {
+                        if (DIAG && J < I) continue;
+                        const float4 x = *reinterpret_cast<const float4 *>(&pr[I]);
+                        const float4 y = *reinterpret_cast<const float4 *>(DIAG ? &pr[J] : &pc[J]);
+                        if (DIAG && I == J) {
+                            accR[I][J] = mf32(x.x, x.x, accR[I][J]);
+                            accR[I][J] = mf32(x.y, x.y, accR[I][J]);
+                            accR[I][J] = mf32(x.z, x.z, accR[I][J]);
+                            accR[I][J] = mf32(x.w, x.w, accR[I][J]);
+                            accI[I][J] = mf32(x.z, x.x, accI[I][J]);
+                            accI[I][J] = mf32(x.w, x.y, accI[I][J]);
+                        } else {
+                            accR[I][J] = mf32(x.x, y.x, accR[I][J]);
+                            accR[I][J] = mf32(x.y, y.y, accR[I][J]);
+                            accI[I][J] = mf32(x.z, y.z, accI[I][J]);
+                            accI[I][J] = mf32(x.w, y.w, accI[I][J]);
+                            acc3[I][J] = mf32(sr[I][0], dc[J][0], acc3[I][J]);
+                            acc3[I][J] = mf32(sr[I][1], dc[J][1], acc3[I][J]);
+                        }
+                    }
+            } else {
+                uint4 qr[RB];
+#pragma unroll
+                for (int I = 0; I < RB; ++I) qr[I] = make_q<PREC>(pr[I]);
+#pragma unroll
+                for (int I = 0; I < RB; ++I)
+#pragma unroll
+                    for (int J = 0; J < RB; ++J) {
+                        if (DIAG && J < I) continue;
+                        const uint4 b = DIAG ? pr[J] : pc[J];
+                        mma<PREC>(accR[I][J], pr[I], b);
+                        mma<PREC>(accI[I][J], qr[I], b);
+                    }
+            }
+        };
+        // set i holds k-block kb + i at the top of a round; in step i of a round
+        // set (i + NBUF - 1) mod NBUF, just freed, is loaded with k-block
+        // kb + i + NBUF - 1 (the last one again past the end) and set i is
+        // multiplied
+        uint4 r[NBUF][RB], c[NBUF][RB];
+#pragma unroll
+        for (int i = 0; i < NBUF - 1; ++i)
+            if (kb0 + i < kb1) load(kb0 + i, r[i], c[i]);
+        int kb = kb0;
+#pragma unroll 1
+        for (; kb + NBUF - 1 < kb1; kb += NBUF) {
+#pragma unroll
+            for (int i = 0; i < NBUF; ++i) {
+                load(min(kb + i + NBUF - 1, kb1 - 1), r[(i + NBUF - 1) % NBUF], c[(i + NBUF - 1) % NBUF]);
+                __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the products
+                compute(r[i], c[i]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < NBUF - 1; ++i)
+            if (kb + i < kb1) compute(r[i], c[i]);
+    }
+
+    // Write the region into partial row obase ([baseline] of one split and
+    // channel); tb is this wave's 16 x 17 floats of LDS (fp32 form only).
+    // The fp32 accumulators are turned into (Re, Im) in place.
+    __device__ __forceinline__ void store(void *partial, int64_t obase, int N, int I0, int J0, float *tb) {
+        const int lane = threadIdx.x & 63;
+        if constexpr (F3M) {
+            // off the diagonal Re = P1 + P2, Im = P3 - P1 + P2; on it
+            // Im = M - M^T, transposed through LDS
+#pragma unroll
+            for (int I = 0; I < RB; ++I)
+#pragma unroll
+                for (int J = 0; J < RB; ++J) {
+                    if (DIAG && J < I) continue;
+                    if (DIAG && I == J) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) tb[(4 * (lane >> 4) + v) * 17 + (lane & 15)] = accI[I][J][v];
+                        wave_lds_sync();
+                        f32x4 mt;
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) mt[v] = tb[(lane & 15) * 17 + 4 * (lane >> 4) + v];
+                        wave_lds_sync();
+                        accI[I][J] = accI[I][J] - mt;
+                    } else {
+                        const f32x4 p1 = accR[I][J], p2 = accI[I][J];
+                        accR[I][J] = p1 + p2;
+                        accI[I][J] = acc3[I][J] - p1 + p2;
+                    }
+                }
+        }
+        // accumulator element v of lane l is row 4*(l/16)+v, column l%16
+#pragma unroll
+        for (int I = 0; I < RB; ++I)
+#pragma unroll
+            for (int J = 0; J < RB; ++J) {
+                if (DIAG && J < I) continue;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int ia = (I0 + I) * 16 + 4 * (lane >> 4) + v;
+                    const int ib = (J0 + J) * 16 + (lane & 15);
+                    if (ia < N && ib < N && ia <= ib) {
+                        const int bl = ia * N - ia * (ia - 1) / 2 + (ib - ia);
+                        store_vis<PREC>(partial, obase + bl, accR[I][J], accI[I][J], v, ia == ib);
+                    }
+                }
+            }
+    }
+};
+
 // One wavefront's share of the X-stage: region `wave % nregions` of channel
 // (wave / nregions) % K over time split wave / (nregions K).  `wave` must be
 // wave-uniform; tb is this wave's 16 x 17 floats of LDS (fp32 form only).
 template <int PREC, int RB, bool DIAG>
 __device__ __forceinline__ void x_wave(const XArgs &a, int wave, float *tb) {
-    typedef typename AccT<PREC>::type acc_t;
-    constexpr bool F3M = PREC == kFP32;   // three-product form
-    const int lane = threadIdx.x & 63;
     if (wave >= a.nregions * a.K * a.nsplit) return;
     const int reg = wave % a.nregions;
     const int rest = wave / a.nregions;
@@ -99,145 +269,10 @@ __device__ __forceinline__ void x_wave(const XArgs &a, int wave, float *tb) {
     const int I0 = a.regions[reg].x, J0 = a.regions[reg].y;
     const int kb0 = (int)((int64_t)sp * a.nkb / a.nsplit);
     const int kb1 = (int)((int64_t)(sp + 1) * a.nkb / a.nsplit);
-
-    // Q form: accR = Re, accI = Im.  fp32: diagonal pair accR = Re, accI = M;
-    // off-diagonal pair accR = P1, accI = P2, acc3 = P3.
-    acc_t accR[RB][RB], accI[RB][RB], acc3[RB][RB];
-#pragma unroll
-    for (int I = 0; I < RB; ++I)
-#pragma unroll
-        for (int J = 0; J < RB; ++J) {
-            accR[I][J] = acc_t{0, 0, 0, 0};
-            accI[I][J] = acc_t{0, 0, 0, 0};
-            acc3[I][J] = acc_t{0, 0, 0, 0};
-        }
-
-    // lane (row r, group g) reads record tq = 4 kb + g of antenna 16 I + r;
-    // a k-block is the (kb mod 4)-th quarter of time block kb / 4
-    const uint4 *base = a.spec + (int64_t)f * kTQB * a.a_pad + (lane >> 4) * a.a_pad + (lane & 15);
-    const int64_t bstride = (int64_t)a.K * kTQB * a.a_pad;
-
-    // two register sets alternate: the records of the next k-block are in
-    // flight while the current one is multiplied
-    auto load = [&](int kb, uint4 *r, uint4 *c) {
-        const uint4 *rec = base + (kb >> 2) * bstride + (kb & 3) * 4 * a.a_pad;
-#pragma unroll
-        for (int I = 0; I < RB; ++I) r[I] = rec[(I0 + I) * 16];
-        if constexpr (!DIAG) {
-#pragma unroll
-            for (int J = 0; J < RB; ++J) c[J] = rec[(J0 + J) * 16];
-        }
-    };
-    auto compute = [&](const uint4 *pr, const uint4 *pc) {
-        if constexpr (F3M) {
-            // record = (re t0, re t1, im t0, im t1)
-            float sr[RB][2], dc[RB][2];
-#pragma unroll
-            for (int I = 0; I < RB; ++I) {
-                const float4 p = *reinterpret_cast<const float4 *>(&pr[I]);
-                sr[I][0] = p.x + p.z;
-                sr[I][1] = p.y + p.w;
-            }
-#pragma unroll
-            for (int J = 0; J < RB; ++J) {
-                const float4 p = *reinterpret_cast<const float4 *>(DIAG ? &pr[J] : &pc[J]);
-                dc[J][0] = p.x - p.z;
-                dc[J][1] = p.y - p.w;
-            }
-#pragma unroll
-            for (int I = 0; I < RB; ++I)
-#pragma unroll
-                for (int J = 0; J < RB; ++J) {
-                    if (DIAG && J < I) continue;
-                    const float4 x = *reinterpret_cast<const float4 *>(&pr[I]);
-                    const float4 y = *reinterpret_cast<const float4 *>(DIAG ? &pr[J] : &pc[J]);
-                    if (DIAG && I == J) {
-                        accR[I][J] = mf32(x.x, x.x, accR[I][J]);
-                        accR[I][J] = mf32(x.y, x.y, accR[I][J]);
-                        accR[I][J] = mf32(x.z, x.z, accR[I][J]);
-                        accR[I][J] = mf32(x.w, x.w, accR[I][J]);
-                        accI[I][J] = mf32(x.z, x.x, accI[I][J]);
-                        accI[I][J] = mf32(x.w, x.y, accI[I][J]);
-                    } else {
-                        accR[I][J] = mf32(x.x, y.x, accR[I][J]);
-                        accR[I][J] = mf32(x.y, y.y, accR[I][J]);
-                        accI[I][J] = mf32(x.z, y.z, accI[I][J]);
-                        accI[I][J] = mf32(x.w, y.w, accI[I][J]);
-                        acc3[I][J] = mf32(sr[I][0], dc[J][0], acc3[I][J]);
-                        acc3[I][J] = mf32(sr[I][1], dc[J][1], acc3[I][J]);
-                    }
-                }
-        } else {
-            uint4 qr[RB];
-#pragma unroll
-            for (int I = 0; I < RB; ++I) qr[I] = make_q<PREC>(pr[I]);
-#pragma unroll
-            for (int I = 0; I < RB; ++I)
-#pragma unroll
-                for (int J = 0; J < RB; ++J) {
-                    if (DIAG && J < I) continue;
-                    const uint4 b = DIAG ? pr[J] : pc[J];
-                    mma<PREC>(accR[I][J], pr[I], b);
-                    mma<PREC>(accI[I][J], qr[I], b);
-                }
-        }
-    };
-    uint4 ar[RB], ac[RB], br[RB], bc[RB];
-    int kb = kb0;
-    if (kb < kb1) load(kb, ar, ac);
-#pragma unroll 1
-    for (; kb + 1 < kb1; kb += 2) {
-        load(kb + 1, br, bc);
-        __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the products
-        compute(ar, ac);
-        load(min(kb + 2, kb1 - 1), ar, ac);
-        __builtin_amdgcn_sched_barrier(0);
-        compute(br, bc);
-    }
-    if (kb < kb1) compute(ar, ac);
-
-    if constexpr (F3M) {
-        // turn the fp32 accumulators into (Re, Im): off the diagonal Re = P1 + P2,
-        // Im = P3 - P1 + P2; on it Im = M - M^T, transposed through LDS
-#pragma unroll
-        for (int I = 0; I < RB; ++I)
-#pragma unroll
-            for (int J = 0; J < RB; ++J) {
-                if (DIAG && J < I) continue;
-                if (DIAG && I == J) {
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) tb[(4 * (lane >> 4) + v) * 17 + (lane & 15)] = accI[I][J][v];
-                    wave_lds_sync();
-                    f32x4 mt;
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) mt[v] = tb[(lane & 15) * 17 + 4 * (lane >> 4) + v];
-                    wave_lds_sync();
-                    accI[I][J] = accI[I][J] - mt;
-                } else {
-                    const f32x4 p1 = accR[I][J], p2 = accI[I][J];
-                    accR[I][J] = p1 + p2;
-                    accI[I][J] = acc3[I][J] - p1 + p2;
-                }
-            }
-    }
-
-    // accumulator element v of lane l is row 4*(l/16)+v, column l%16
-    const int64_t obase = ((int64_t)sp * a.K + f) * a.nb;
-#pragma unroll
-    for (int I = 0; I < RB; ++I)
-#pragma unroll
-        for (int J = 0; J < RB; ++J) {
-            if (DIAG && J < I) continue;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int ia = (I0 + I) * 16 + 4 * (lane >> 4) + v;
-                const int ib = (J0 + J) * 16 + (lane & 15);
-                if (ia < a.N && ib < a.N && ia <= ib) {
-                    const int bl = ia * a.N - ia * (ia - 1) / 2 + (ib - ia);
-                    store_vis<PREC>(a.partial, obase + bl, accR[I][J], accI[I][J], v, ia == ib);
-                }
-            }
-        }
+    XRegion<PREC, RB, DIAG> x;
+    x.zero();
+    x.run(a.spec, a.K, a.a_pad, f, I0, J0, kb0, kb1);
+    x.store(a.partial, ((int64_t)sp * a.K + f) * a.nb, a.N, I0, J0, tb);
 }
 
 // ------------------------------------------------------------ LDS groups

@@ -43,11 +43,14 @@ def f_lds_bytes(K: int, prec: str, group: int) -> int:
     return record_times(prec) * group * slot * 8 + fpr * K
 
 
-def key(N: int, K: int, S: int, prec: str, batch=False) -> str:
+def key(N: int, K: int, S: int, prec: str, batch=False, mode: Optional[str] = None) -> str:
     """Table key; batch is False (a single job), True or "persistent" (a job
     of the persistent batch kernel) or "branches" (a job on a branch of a
-    batch graph, whose chunk and F group are fixed)."""
+    batch graph, whose chunk and F group are fixed); mode "fused" is a single
+    job on the fused pipeline (chunk, ring slots, F workgroups per CU)."""
     suffix = "" if not batch else (":branches" if batch == "branches" else ":batch")
+    if mode == "fused":
+        suffix += ":fused"
     return f"{ARCH}:N={N}:K={K}:S={S}:{prec}" + suffix
 
 
@@ -74,8 +77,8 @@ def load_table(path: str = TABLE) -> Dict[str, dict]:
     return {}
 
 
-def lookup(N: int, K: int, S: int, prec: str, batch=False, path: str = TABLE) -> Optional[dict]:
-    return load_table(path).get(key(N, K, S, prec, batch))
+def lookup(N: int, K: int, S: int, prec: str, batch=False, path: str = TABLE, mode: Optional[str] = None) -> Optional[dict]:
+    return load_table(path).get(key(N, K, S, prec, batch, mode))
 
 
 def _time_single(corr, torch, N, K, S, prec, tiles, x, reps=3, warm=1) -> Dict[str, float]:
