@@ -61,6 +61,48 @@ def measured_traffic(kernel, spectra_per_launch):
     return entry["fetch_bytes"] + entry["write_bytes"]
 
 
+def counted_valu(kernel):
+    """VALU lane-operations per antenna-sample of an F-stage kernel from the
+    committed rocprofv3 counter run (profiles/valu.json), or None when the
+    kernel's source has changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "valu.json")
+    if not os.path.exists(path):
+        return None
+    entry = json.load(open(path)).get(kernel)
+    if entry is None:
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel.split("<")[0]]:
+        h.update(open(os.path.join(ROOT, "paper_1102_0148_amd", "csrc", f), "rb").read())
+    if h.hexdigest() != entry["source_sha256"]:
+        return None
+    return entry["valu_lane_ops_per_antenna_sample"]
+
+
+# VALU issue peak without packed-fp32 forms: 256 CUs x 64 lanes x 2.4 GHz
+VALU_LANE_OPS_PEAK = 256 * 64 * 2.4e9
+
+
+def f_stage_bounds(metrics, name, f_ms, group):
+    """The F-stage of one form against its two candidate bounds: HBM (0.5 B
+    read + the record bytes written per antenna-sample) and VALU issue (lane
+    operations per antenna-sample counted by rocprofv3, over the event-timed
+    duration)."""
+    rec = {"fp32": 4.0, "fp16": 2.0, "int8": 1.0, "int16": 2.0}[name]
+    a_s = metrics.antenna_samples(N_ANT, TWO_K, S_INT)
+    gbs = a_s * (0.5 + rec) / (f_ms * 1e-3) / 1e9
+    out = {"hbm": {"achieved_gbs": round(gbs, 1), "frac": round(gbs / PEAK["hbm_gbs"], 4),
+                   "bytes_per_antenna_sample": 0.5 + rec}}
+    prec_code = {"fp32": 0, "fp16": 1, "int8": 2, "int16": 3}[name]
+    per_as = counted_valu(f"fstage_kernel<256, {prec_code}, {group}, false>")
+    if per_as is not None:
+        rate = per_as * a_s / (f_ms * 1e-3)
+        out["alu"] = {"valu_lane_ops_per_antenna_sample": per_as, "achieved_lane_ops_per_s": float("%.4g" % rate),
+                      "peak_lane_ops_per_s": VALU_LANE_OPS_PEAK, "frac": round(rate / VALU_LANE_OPS_PEAK, 4)}
+    return out
+
+
 def make_inputs(device):
     import synth
     recipe = synth.recipe_plain(N=N_ANT, two_k=TWO_K, rho=0.05, seed=1)
@@ -71,8 +113,8 @@ def make_inputs(device):
     return bufs
 
 
-def run_form(corr, torch, precision, inputs, steps, warmup, timing=False, tracking=None):
-    c = corr.Correlator(N_ANT, K, S_INT, precision=precision, tiles="auto")
+def run_form(corr, torch, precision, inputs, steps, warmup, timing=False, tracking=None, pipeline=None):
+    c = corr.Correlator(N_ANT, K, S_INT, precision=precision, tiles="auto", pipeline=pipeline)
     if tracking:
         c.set_tracking(**tracking)
     dst = torch.empty(c.nb * K * 2, dtype=torch.float64, device="cuda")
@@ -123,6 +165,26 @@ def tracking_leg(corr, torch, metrics, inputs, steps, warmup, forms):
                      "f_ms_per_integration": round(stats["ms_f"] / n_int, 4),
                      "untracked_f_ms_per_integration": forms[name]["ms_per_integration"]["f"]}
         log(f"[bench] tracking {name}: {out[name]}")
+    return out
+
+
+def fused_leg(corr, torch, metrics, inputs, steps, warmup, forms):
+    """The same step through the fused pipeline (one persistent F + X kernel
+    per integration, records handed over through a cache-sized ring), with
+    its default parameters, against the staged pipeline's step."""
+    a_s = N_INT * metrics.antenna_samples(N_ANT, TWO_K, S_INT)
+    out = {}
+    for name in ("fp32", "fp16", "int8"):
+        if name not in forms:
+            continue
+        ms, _, stats, tiles = run_form(corr, torch, name, inputs, steps, warmup, timing=True, pipeline="fused")
+        n_int = steps * N_INT
+        out[name] = {"antenna_msps": round(a_s / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4),
+                     "ms_fused_kernel_per_integration": round(stats["ms_fused"] / n_int, 4),
+                     "ms_dump_per_integration": round(stats["ms_dump"] / n_int, 4),
+                     "tiles": tiles,
+                     "speedup_vs_staged": round(forms[name]["ms_per_step"] / ms, 3)}
+        log(f"[bench] fused {name}: {out[name]}")
     return out
 
 
@@ -372,7 +434,9 @@ def main():
     ap.add_argument("--cpu-spectra-one-thread", type=int, default=4096)
     ap.add_argument("--cpu-spectra-large-n", type=int, default=1024)
     ap.add_argument("--forms", default="fp32,fp16,int8,int16")
-    ap.add_argument("--no-extra", action="store_true", help="skip the large-N and batch workloads")
+    ap.add_argument("--no-extra", action="store_true", help="skip every workload beyond the headline step")
+    ap.add_argument("--legs", default="fused,tracking,ingest,large_n,batch",
+                    help="extra workloads to run after the headline step (comma list)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (scale reference for HBM counters)")
     args = ap.parse_args()
@@ -415,6 +479,7 @@ def main():
             "tiles": tiles,
             "x_mfma": x_mfma(metrics, N_ANT, K, S_INT, name, x_ms),
         }
+        forms[name]["f_stage"] = f_stage_bounds(metrics, name, f_ms, tiles["f_group"])
         if name in ("int8", "int16"):
             forms[name]["saturated_fraction"] = stats["int8_saturated"] / max(
                 1, (args.steps + args.warmup) * N_INT * S_INT * N_ANT * K * 2)
@@ -473,12 +538,18 @@ def main():
         "forms": forms,
         "roofline": roof,
     }
-    if not args.no_extra:
+    legs = set() if args.no_extra else set(x for x in args.legs.split(",") if x)
+    if "fused" in legs:
+        out["fused"] = fused_leg(corr, torch, metrics, inputs, max(2, args.steps // 2), 1, forms)
+    if "tracking" in legs:
         out["tracking"] = tracking_leg(corr, torch, metrics, inputs, max(2, args.steps // 3), 1, forms)
+    if "ingest" in legs:
         out["ingest"] = ingest_leg(corr, torch, inputs[0])
-        del inputs
-        torch.cuda.empty_cache()
+    del inputs
+    torch.cuda.empty_cache()
+    if "large_n" in legs:
         out["large_n"] = large_n(corr, torch, metrics, max(2, args.steps // 3), 1)
+    if "batch" in legs:
         out["batch"] = batch(corr, torch, metrics, max(3, args.steps // 3), 1)
     if not args.no_cpu_baseline:
         import numpy as np

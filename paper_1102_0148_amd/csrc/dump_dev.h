@@ -29,6 +29,9 @@ __device__ __forceinline__ float scale_one(const float *power, int nparts, int a
                                            float codes_per_rms) {
     const int ant = e / K, c = e % K;
     float p = 0.0f;
+    // the adds stay in order; unrolling lets the loads of a run of partials
+    // be in flight together (one at a time the sum waited on each)
+#pragma unroll 16
     for (int i = 0; i < nparts; ++i) p += power[((int64_t)i * a_pad + ant) * K + c];
     float sc = 1.0f;
     if (p > 0.0f && W > 0) {
