@@ -143,6 +143,7 @@ def run_form(corr, torch, precision, inputs, steps, warmup, timing=False, tracki
     ms = t0.elapsed_time(t1)
     stats = c.stats()
     tiles = c.tiles()
+    tiles["pipeline"] = c.pipeline
     c.close()
     return ms / steps, wall / steps * 1e3, stats, tiles
 
@@ -169,22 +170,31 @@ def tracking_leg(corr, torch, metrics, inputs, steps, warmup, forms):
 
 
 def fused_leg(corr, torch, metrics, inputs, steps, warmup, forms):
-    """The same step through the fused pipeline (one persistent F + X kernel
-    per integration, records handed over through a cache-sized ring), with
-    its default parameters, against the staged pipeline's step."""
+    """Both pipelines of the fp32, fp16 and int8 steps: the staged one (F
+    launch, X launch and dump per chunk) and the fused one (one persistent
+    F + X kernel per integration, records handed over through a cache-sized
+    ring, the autotuner's parameters).  The form above ran the pipeline the
+    autotuner picked; this leg runs the other one."""
     a_s = N_INT * metrics.antenna_samples(N_ANT, TWO_K, S_INT)
     out = {}
     for name in ("fp32", "fp16", "int8"):
         if name not in forms:
             continue
-        ms, _, stats, tiles = run_form(corr, torch, name, inputs, steps, warmup, timing=True, pipeline="fused")
+        ran = forms[name]["tiles"]["pipeline"]
+        other = "staged" if ran == "fused" else "fused"
+        ms, _, stats, tiles = run_form(corr, torch, name, inputs, steps, warmup, timing=True, pipeline=other)
         n_int = steps * N_INT
-        out[name] = {"antenna_msps": round(a_s / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4),
-                     "ms_fused_kernel_per_integration": round(stats["ms_fused"] / n_int, 4),
-                     "ms_dump_per_integration": round(stats["ms_dump"] / n_int, 4),
-                     "tiles": tiles,
-                     "speedup_vs_staged": round(forms[name]["ms_per_step"] / ms, 3)}
-        log(f"[bench] fused {name}: {out[name]}")
+        times = {ran: forms[name]["ms_per_step"], other: round(ms, 4)}
+        out[name] = {"staged": {"ms_per_step": times["staged"],
+                                "antenna_msps": round(a_s / (times["staged"] * 1e-3) / 1e6, 1)},
+                     "fused": {"ms_per_step": times["fused"],
+                               "antenna_msps": round(a_s / (times["fused"] * 1e-3) / 1e6, 1)},
+                     "fused_speedup_vs_staged": round(times["staged"] / times["fused"], 3),
+                     "autotuner_pipeline": ran}
+        if other == "fused":
+            out[name]["fused"]["ms_kernel_per_integration"] = round(stats["ms_fused"] / n_int, 4)
+            out[name]["fused"]["tiles"] = tiles
+        log(f"[bench] pipelines {name}: {out[name]}")
     return out
 
 
@@ -468,6 +478,23 @@ def main():
         n_int = args.steps * N_INT
         x_ms = stats["ms_x"] / n_int
         f_ms = stats["ms_f"] / n_int
+        if tiles["pipeline"] == "fused":
+            # the autotuner picked the fused pipeline: one F + X kernel
+            forms[name] = {
+                "antenna_msps": round(a_s_per_step / (ms * 1e-3) / 1e6, 1),
+                "ms_per_step": round(ms, 4),
+                "x_tops": None,
+                "ms_per_integration": {"fused": round(stats["ms_fused"] / n_int, 4),
+                                       "dump": round(stats["ms_dump"] / n_int, 4),
+                                       "calib": round(stats["ms_calib"] / n_int, 4)},
+                "launches_per_integration": {"fused": stats["launches_fused"] // n_int},
+                "tiles": tiles,
+            }
+            if name in ("int8", "int16"):
+                forms[name]["saturated_fraction"] = stats["int8_saturated"] / max(
+                    1, (args.steps + args.warmup) * N_INT * S_INT * N_ANT * K * 2)
+            log(f"[bench] {name}: {forms[name]}")
+            continue
         forms[name] = {
             "antenna_msps": round(a_s_per_step / (ms * 1e-3) / 1e6, 1),
             "ms_per_step": round(ms, 4),
@@ -497,7 +524,14 @@ def main():
     st = head["ms_per_integration"]
     launches = head["launches_per_integration"]
     chunk = head["tiles"]["chunk_spectra"]
-    if st["x"] >= st["f"]:
+    if "fused" in st:
+        # the fused kernel does F and X together; priced by its useful X flops
+        flops = metrics.x_ops(N_ANT, K, S_INT)
+        achieved = flops / (st["fused"] * 1e-3) / 1e12
+        roof = {"kernel": "fx_kernel (fused F + X, fp32)", "bound": "mfma", "achieved": round(achieved, 2),
+                "peak": PEAK["fp32_tflops"], "unit": "TFLOP/s", "frac": round(achieved / PEAK["fp32_tflops"], 4),
+                "traffic": None, "per_launch": {"useful_flops": flops, "avg_ms": st["fused"]}}
+    elif st["x"] >= st["f"]:
         per_launch_ms = st["x"] / max(1, launches["x"])
         flops = metrics.x_ops(N_ANT, K, chunk)
         achieved = flops / (per_launch_ms * 1e-3) / 1e12

@@ -300,17 +300,26 @@ class Correlator:
     def __init__(self, N: int, K: int, n_spectra: int, precision="fp32", tiles=None, pipeline=None):
         """tiles: None (library defaults), "auto" (the autotuner's table,
         defaults where it has no entry) or a dict of corr_tiles fields.
-        pipeline: None / "staged", or "fused" optionally with its parameters
-        as a dict {"chunk_spectra", "ring_slots", "f_workgroups_per_cu"}
-        (with tiles="auto", the autotuner's fused entry when it has one)."""
+        pipeline: None (with tiles="auto": the pipeline the autotuner found
+        faster for this shape, else staged), "staged", or "fused" optionally
+        with its parameters as a dict {"chunk_spectra", "ring_slots",
+        "f_workgroups_per_cu"} (with tiles="auto", the autotuner's fused entry
+        when it has one)."""
         self.N, self.K, self.S = N, K, n_spectra
         self.nb = n_baselines(N)
+        self._fused = False
         self.h = corr_create(N, K, n_spectra)
         try:
             mode = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
             corr_set_precision(self.h, mode)
             self.precision = mode
             name = {v: k for k, v in PRECISIONS.items()}[mode]
+            auto = isinstance(tiles, str) and tiles == "auto"
+            if pipeline is None and auto:
+                from . import tune
+                found = tune.lookup(N, K, n_spectra, name)
+                if found and found.get("pipeline") == "fused":
+                    pipeline = "fused"
             fused = pipeline == "fused" or isinstance(pipeline, dict)
             if fused:
                 params = dict(pipeline) if isinstance(pipeline, dict) else {}
@@ -321,12 +330,14 @@ class Correlator:
                         if found else {}
                 corr_set_pipeline(self.h, CORR_PIPELINE_FUSED, **params)
                 tiles = None
+                self._fused = True
             elif pipeline not in (None, "staged"):
                 raise ValueError(f"unknown pipeline {pipeline!r}")
             if isinstance(tiles, str) and tiles == "auto":
                 from . import tune
                 found = tune.lookup(N, K, n_spectra, name)
-                tiles = {k: found[k] for k in ("chunk_spectra", "x_splits", "f_group")} if found else None
+                tiles = {k: found[k] for k in ("chunk_spectra", "x_splits", "f_group")} \
+                    if found and "chunk_spectra" in found else None
             if tiles:
                 corr_set_tiles(self.h, **tiles)
         except Exception:
@@ -346,6 +357,10 @@ class Correlator:
 
     def tiles(self) -> dict:
         return corr_get_tiles(self.h)
+
+    @property
+    def pipeline(self) -> str:
+        return "fused" if self._fused else "staged"
 
     def process(self, packed, stream=None):
         """packed: uint8 CUDA tensor holding n_spectra*N*K bytes."""

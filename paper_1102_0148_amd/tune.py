@@ -3,7 +3,10 @@
 For one job shape (N antennas, K channels, n_spectra, precision) it times
 every candidate (chunk_spectra, x_splits, f_group) with the library's own
 stage timers (HIP events on the launch stream) over a few integrations of
-synthetic input, and keeps the fastest.  Jobs of the persistent batch kernel
+synthetic input, and keeps the fastest; where the fused pipeline covers the
+shape it also times the fused choices (ring chunk, slots, F workgroups per
+CU) end to end against the best staged tiles and records which pipeline
+Correlator(tiles="auto") should run.  Jobs of the persistent batch kernel
 (one chunk per job, the F-stage group fixed) are tuned over x_splits in a
 batch of their own; a branch of a batch graph runs the single-job kernels and
 takes the single-job entries.  Results go to a JSON table keyed by (arch, N,
@@ -151,6 +154,74 @@ def tune_single(N: int, K: int, S: int, prec: str, log=print) -> Tuple[dict, flo
     return best, best_ms, results + final
 
 
+def fused_candidates(N: int, K: int, S: int, prec: str) -> List[dict]:
+    """Fused-pipeline choices: ring slots of about 24 to 96 MB of records,
+    two or three slots, the default or one F workgroup per CU.  The fused
+    kernel covers fp32, fp16 and int8 at N <= 48."""
+    if prec not in ("fp32", "fp16", "int8") or N > 48:
+        return []
+    a_pad = 16 * ((N + 15) // 16)
+    per_spectrum = a_pad * K * 16 // record_times(prec)
+    whole = (S + 63) // 64 * 64
+    chunks = sorted({min(whole, max(64, (mb << 20) // per_spectrum // 64 * 64)) for mb in (24, 48, 72, 96)})
+    return [{"chunk_spectra": c, "ring_slots": r, "f_workgroups_per_cu": f}
+            for c in chunks for r in (2, 3) for f in (0, 1)]
+
+
+def _time_e2e(corr, torch, N, K, S, prec, x, tiles=None, pipeline=None, reps=4, warm=1) -> float:
+    """End-to-end time of one integration (process and an asynchronous read,
+    HIP events around them), for comparing pipelines."""
+    c = corr.Correlator(N, K, S, precision=prec, tiles=tiles, pipeline=pipeline)
+    dst = torch.empty(c.nb * K * 2, dtype=torch.float64, device="cuda")
+    try:
+        for _ in range(warm):
+            c.process(x)
+            c.read_cps_async(dst)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            c.process(x)
+            c.read_cps_async(dst)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+    finally:
+        c.close()
+        del dst
+        torch.cuda.empty_cache()
+
+
+def tune_pipeline(N: int, K: int, S: int, prec: str, staged: dict, log=print) -> Tuple[Optional[dict], float, float]:
+    """Every fused choice timed once end to end, then the three fastest and
+    the staged pipeline's best tiles in turn over three rounds (medians).
+    Returns the best fused choice (None where the kernel does not cover the
+    shape), its median time and the staged median."""
+    import torch
+    import paper_1102_0148_amd as corr
+    import synth
+    cands = fused_candidates(N, K, S, prec)
+    if not cands:
+        return None, float("inf"), float("inf")
+    x = synth.packed(synth.recipe_plain(N=N, two_k=2 * K, seed=11), 0, S, device="cuda").contiguous()
+    first = []
+    for p in cands:
+        ms = _time_e2e(corr, torch, N, K, S, prec, x, pipeline=p)
+        first.append((p, ms))
+        log(f"  fused {prec} N={N} K={K} {p} {ms:.4f} ms")
+    top = [p for p, _ in sorted(first, key=lambda r: r[1])[:3]]
+    seen: Dict[str, List[float]] = {}
+    for r in range(3):
+        for p in top:
+            seen.setdefault(json.dumps(p, sort_keys=True), []).append(
+                _time_e2e(corr, torch, N, K, S, prec, x, pipeline=p))
+        seen.setdefault("staged", []).append(_time_e2e(corr, torch, N, K, S, prec, x, tiles=staged))
+    staged_ms = _median(seen.pop("staged"))
+    best = min(((json.loads(k), _median(v)) for k, v in seen.items()), key=lambda r: r[1])
+    log(f"  fused {prec} N={N} K={K} best {best[0]} {best[1]:.4f} ms; staged {staged_ms:.4f} ms")
+    return best[0], best[1], staged_ms
+
+
 TIE = 0.01
 
 
@@ -204,6 +275,8 @@ def main(argv: Optional[Iterable[str]] = None):
                                        "32:1024:16384,44:256:16384,64:512:16384,96:256:16384")
     ap.add_argument("--batch-precisions", default="int8,fp32")
     ap.add_argument("--batch-modes", default="persistent")
+    ap.add_argument("--pipeline-only", action="store_true",
+                    help="keep the table's staged tiles of each single shape and only choose the pipeline")
     args = ap.parse_args(argv)
     sys.path.insert(0, os.path.dirname(HERE))
     import torch
@@ -212,8 +285,21 @@ def main(argv: Optional[Iterable[str]] = None):
     for item in filter(None, args.single.split(",")):
         N, K, S, prec = item.split(":")
         N, K, S = int(N), int(K), int(S)
-        best, ms, _ = tune_single(N, K, S, prec)
-        table[key(N, K, S, prec)] = dict(best, ms=round(ms, 4))
+        old = table.get(key(N, K, S, prec))
+        if args.pipeline_only and old and "chunk_spectra" in old:
+            best = {k: old[k] for k in ("chunk_spectra", "x_splits", "f_group")}
+            ms = old.get("ms", 0.0)
+        else:
+            best, ms, _ = tune_single(N, K, S, prec)
+        entry = dict(best, ms=round(ms, 4), pipeline="staged")
+        fbest, fms, sms = tune_pipeline(N, K, S, prec, best)
+        if fbest is not None:
+            table[key(N, K, S, prec, mode="fused")] = dict(fbest, ms=round(fms, 4))
+            # the fused pipeline where it is faster end to end by more than a tie
+            if fms < sms * (1 - TIE):
+                entry["pipeline"] = "fused"
+            entry["e2e_ms"] = {"staged": round(sms, 4), "fused": round(fms, 4)}
+        table[key(N, K, S, prec)] = entry
         print(f"best {key(N, K, S, prec)}: {table[key(N, K, S, prec)]}", flush=True)
         with open(args.out, "w") as f:
             json.dump(table, f, indent=1, sort_keys=True)
