@@ -148,10 +148,12 @@ def run_form(corr, torch, precision, inputs, steps, warmup, timing=False, tracki
     return ms / steps, wall / steps * 1e3, stats, tiles
 
 
-def tracking_leg(corr, torch, metrics, inputs, steps, warmup, forms):
+def tracking_leg(corr, torch, metrics, inputs, steps, warmup, forms, pipelines=None):
     """The headline step with per-antenna delay and phase tracking switched on
     (delays up to 50 samples, with rates), in each form, against the same
-    step without it."""
+    step without it.  Tracking runs in the staged pipeline; a form whose
+    tuned pipeline is the fused one compares with its staged F time from the
+    pipelines leg."""
     import numpy as np
     rng = np.random.default_rng(1)
     model = dict(delay=rng.uniform(-50, 50, N_ANT), delay_rate=rng.uniform(-1e-3, 1e-3, N_ANT),
@@ -160,11 +162,14 @@ def tracking_leg(corr, torch, metrics, inputs, steps, warmup, forms):
     out = {"model": "per-antenna delay U(-50, 50) samples, rate U(-1e-3, 1e-3) samples/spectrum, "
                     "phase U(-1, 1) turns, rate U(-1e-4, 1e-4) turns/spectrum"}
     for name in forms:
-        ms, _, stats, _ = run_form(corr, torch, name, inputs, steps, warmup, timing=True, tracking=model)
+        ms, _, stats, tiles = run_form(corr, torch, name, inputs, steps, warmup, timing=True, tracking=model)
         n_int = steps * N_INT
+        untracked = forms[name]["ms_per_integration"].get("f")
+        if untracked is None and pipelines and name in pipelines:
+            untracked = pipelines[name]["staged"].get("f_ms_per_integration")
         out[name] = {"antenna_msps": round(a_s / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4),
-                     "f_ms_per_integration": round(stats["ms_f"] / n_int, 4),
-                     "untracked_f_ms_per_integration": forms[name]["ms_per_integration"]["f"]}
+                     "pipeline": tiles["pipeline"], "f_ms_per_integration": round(stats["ms_f"] / n_int, 4),
+                     "untracked_f_ms_per_integration": untracked}
         log(f"[bench] tracking {name}: {out[name]}")
     return out
 
@@ -194,6 +199,9 @@ def fused_leg(corr, torch, metrics, inputs, steps, warmup, forms):
         if other == "fused":
             out[name]["fused"]["ms_kernel_per_integration"] = round(stats["ms_fused"] / n_int, 4)
             out[name]["fused"]["tiles"] = tiles
+        else:
+            out[name]["staged"]["f_ms_per_integration"] = round(stats["ms_f"] / n_int, 4)
+            out[name]["staged"]["tiles"] = tiles
         log(f"[bench] pipelines {name}: {out[name]}")
     return out
 
@@ -576,7 +584,8 @@ def main():
     if "fused" in legs:
         out["fused"] = fused_leg(corr, torch, metrics, inputs, max(2, args.steps // 2), 1, forms)
     if "tracking" in legs:
-        out["tracking"] = tracking_leg(corr, torch, metrics, inputs, max(2, args.steps // 3), 1, forms)
+        out["tracking"] = tracking_leg(corr, torch, metrics, inputs, max(2, args.steps // 3), 1, forms,
+                                       out.get("fused"))
     if "ingest" in legs:
         out["ingest"] = ingest_leg(corr, torch, inputs[0])
     del inputs

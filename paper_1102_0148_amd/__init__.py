@@ -304,10 +304,13 @@ class Correlator:
         faster for this shape, else staged), "staged", or "fused" optionally
         with its parameters as a dict {"chunk_spectra", "ring_slots",
         "f_workgroups_per_cu"} (with tiles="auto", the autotuner's fused entry
-        when it has one)."""
+        when it has one). A fused pipeline that only the autotuner chose gives
+        way to the staged one with its tuned tiles when tracking is switched
+        on before the first process() (the fused kernel does not track)."""
         self.N, self.K, self.S = N, K, n_spectra
         self.nb = n_baselines(N)
         self._fused = False
+        self._staged_fallback = None
         self.h = corr_create(N, K, n_spectra)
         try:
             mode = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -315,11 +318,12 @@ class Correlator:
             self.precision = mode
             name = {v: k for k, v in PRECISIONS.items()}[mode]
             auto = isinstance(tiles, str) and tiles == "auto"
+            chosen = False
             if pipeline is None and auto:
                 from . import tune
-                found = tune.lookup(N, K, n_spectra, name)
-                if found and found.get("pipeline") == "fused":
-                    pipeline = "fused"
+                staged = tune.lookup(N, K, n_spectra, name)
+                if staged and staged.get("pipeline") == "fused":
+                    pipeline, chosen = "fused", True
             fused = pipeline == "fused" or isinstance(pipeline, dict)
             if fused:
                 params = dict(pipeline) if isinstance(pipeline, dict) else {}
@@ -329,6 +333,9 @@ class Correlator:
                     params = {k: found[k] for k in ("chunk_spectra", "ring_slots", "f_workgroups_per_cu")} \
                         if found else {}
                 corr_set_pipeline(self.h, CORR_PIPELINE_FUSED, **params)
+                if chosen:
+                    self._staged_fallback = {k: staged[k] for k in ("chunk_spectra", "x_splits", "f_group")} \
+                        if "x_splits" in staged else {}
                 tiles = None
                 self._fused = True
             elif pipeline not in (None, "staged"):
@@ -387,6 +394,12 @@ class Correlator:
         (turns) and phase rate (turns per spectrum) applied to the spectra
         before accumulation, from the next process() on; no arguments switch
         tracking off."""
+        on = any(v is not None for v in (delay, delay_rate, phase, phase_rate))
+        if on and self._fused and self._staged_fallback is not None:
+            corr_set_pipeline(self.h, CORR_PIPELINE_STAGED)
+            if self._staged_fallback:
+                corr_set_tiles(self.h, **self._staged_fallback)
+            self._fused, self._staged_fallback = False, None
         corr_set_tracking(self.h, delay, delay_rate, phase, phase_rate, N=self.N)
 
     def spectra_bytes(self, n_spectra: int) -> int:

@@ -119,3 +119,29 @@ def test_fused_refuses_what_it_does_not_cover():
     with pytest.raises(corr.CorrError) as e:
         corr.corr_set_pipeline(c.h, 5)
     assert e.value.code == corr.CORR_EINVAL
+
+
+def test_autotuned_fused_gives_way_to_tracking():
+    """Where the autotuner table picked the fused pipeline (fp16, N = 44,
+    512-point, 65536 spectra), switching tracking on before the first
+    process() moves the handle to the staged pipeline with the table's staged
+    tiles; an explicit fused request keeps refusing tracking."""
+    from paper_1102_0148_amd import tune
+    N, K, S = 44, 256, 65536
+    found = tune.lookup(N, K, S, "fp16")
+    if not found or found.get("pipeline") != "fused":
+        pytest.skip("the autotuner table does not pick the fused pipeline for this shape")
+    c = corr.Correlator(N, K, S, precision="fp16", tiles="auto")
+    assert c.pipeline == "fused"
+    c.set_tracking(delay=np.full(N, 3.0))
+    assert c.pipeline == "staged"
+    assert {k: c.tiles()[k] for k in ("chunk_spectra", "x_splits", "f_group")} == \
+        {k: found[k] for k in ("chunk_spectra", "x_splits", "f_group")}
+    x = torch.zeros(S * N * K, dtype=torch.uint8, device="cuda")
+    c.process(x)
+    assert np.all(c.read_cps_raw() == 0)
+    e = corr.Correlator(N, K, S, precision="fp16", pipeline="fused")
+    e.set_tracking(delay=np.full(N, 3.0))
+    with pytest.raises(corr.CorrError) as err:
+        e.process(x)
+    assert err.value.code == corr.CORR_EINVAL
