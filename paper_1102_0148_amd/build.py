@@ -20,11 +20,15 @@ ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-Wno-unused-result"]
+# Units holding the F-stage, whose transform feeds matrix-product results
+# straight back into vector arithmetic: the products write vector registers
+# (the accumulation-register form costs a copy of every result).
+UNIT_FLAGS = {src: ["-mllvm", "-amdgpu-mfma-vgpr-form"] for src in ("fstage.hip", "fused.hip", "batch.hip")}
 
 
 def _compile(src, verbose):
     obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
-    cmd = ["hipcc", *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = ["hipcc", *FLAGS, *UNIT_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -19,6 +19,7 @@
 // 16-byte records [re x TS][im x TS], GA records (GA*16 bytes) contiguous
 // per channel.  Power mode sums |X|^2 over the calibration window instead.
 #pragma once
+#include <type_traits>
 #include "corr_internal.h"
 
 namespace corr {
@@ -162,7 +163,8 @@ __device__ __forceinline__ void pass_twiddles(int j, int p, const float2 *twM, f
 
 // A lane's twiddles for every pass after the first: radix 16 (8 for M = 128)
 // after 16 points, then radix 2 (M = 512) or 4 (M = 1024) after 256.  They
-// depend only on the lane, so a workgroup loads them once.
+// depend only on the lane, so a workgroup loads them once.  (M = 256 runs on
+// the matrix cores and holds their operands instead.)
 template <int M>
 struct PassTw {
     static constexpr int R2 = M == 128 ? 8 : 16;
@@ -177,9 +179,186 @@ struct PassTw {
     }
 };
 
+// The 256-point transform on the matrix cores.  With z[16 s + f] (s, f < 16)
+//   Y[f][c]     = sum_s W16^(s c) z[16 s + f],
+//   Y'[f][c]    = W256^(f c) Y[f][c],
+//   Z[c + 16 d] = sum_f W16^(f d) Y'[f][c],
+// both 16-point DFTs are real 16 x 32 by 32 x 16 products, one transform per
+// wavefront at a time, on v_mfma_f32_16x16x32_f16: lane (j = lane mod 16,
+// g = lane / 16) holds row j of the left operand and column j of the right
+// one over contraction positions 8g .. 8g + 7, i.e. (point 4g + i, re / im)
+// for i < 4, and gets rows 4g + i of column j of the result.  The real form of
+// W16 in that layout is the same register set in both products: the right
+// operand of the first (contraction s, column c = j) and the left operand of
+// the second (row d = j, contraction f).  Each DFT is summed from f16 halves,
+// W16 = hi + lo and Y' = hi + lo, with the products of halves exact in the
+// f32 accumulator; the dropped lo * lo terms and the rounding of the lo
+// halves are of order 2^-21 of the result.  The 4-bit samples are exact in
+// f16.  Bins 0 and 128 see only the entries +-1 and 0 (hi exact, lo zero) and
+// stay exact.  The first product's result is already the second one's right
+// operand in the same lanes: no exchange between the passes.
+//
+// The 512-point transform is one radix-2 step (decimation in time) after two
+// such transforms of the even and the odd samples, E and O:
+//   Z[q] = E[q] + W512^q O[q],  Z[q + 256] = E[q] - W512^q O[q],  q < 256,
+// where lane (j, g) already holds E and O at the same q = j + 16 (4g + i).
+typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
+typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+// The matrix-core transform serves the reduced-precision records at 256 and
+// 512 points, where the F-stage is bound by vector work.  The float32 records
+// (bound by their HBM writes, where it measured a few percent slower) and the
+// calibration power sums keep the vector transform.
+template <int M, int PREC> constexpr bool mfma_fft() { return (M == 256 || M == 512) && PREC != kFP32; }
+
+template <int M>
+struct MfmaFft {
+    static constexpr int P = M / 256;  // 256-point transforms per block
+    h8_t dh[2], dl[2];  // W16, real form: [0] real outputs, [1] imaginary outputs
+    float2 w[4];        // W256^(f c), f = 4g + i, c = j
+    float2 w2[P == 2 ? 4 : 1];  // W512^q, q = j + 16 (4g + i)
+    uint32_t sel01[P], sel23[P];
+    __device__ __forceinline__ void load(int, const float2 *twM) {
+        const int lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int s = 4 * g + i;
+            // twM[e] = exp(-2 pi i e / M) = (cos t, -sin t); the real form of
+            // multiplication by it is [cos t, sin t] -> re, [-sin t, cos t] -> im
+            const float2 t = twM[((s * j) & 15) * (M / 16)];
+            const float v[2][2] = {{t.x, -t.y}, {t.y, t.x}};
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const _Float16 h = (_Float16)v[b][c];
+                    dh[b][2 * i + c] = h;
+                    dl[b][2 * i + c] = (_Float16)(v[b][c] - (float)h);
+                }
+            w[i] = twM[((s * j) & 255) * (M / 256)];
+            if constexpr (P == 2) w2[i] = twM[j + 16 * s];
+        }
+        // byte b of four dwords -> one dword: b = j mod 4 (256 points), or
+        // 2 (j mod 2) + p for the even (p = 0) and odd (p = 1) samples
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const uint32_t b = P == 1 ? (j & 3) : 2 * (j & 1) + p;
+            sel01[p] = b | (b + 4) << 8 | 0x0c0c0000u;
+            sel23[p] = 0x0c0cu | b << 16 | (b + 4) << 24;
+        }
+    }
+};
+
+__device__ __forceinline__ f4_t mfma_h(h8_t a, h8_t b, f4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
+// 256 points, the lane's four samples z[16 (4g + i) + j] packed one per byte
+// of p, to the lane's four outputs Z[j + 16 (4g + i)] (zr, zi).
+template <int M>
+__device__ __forceinline__ void dft256_mfma(uint32_t p, const MfmaFft<M> &k, f4_t &zr, f4_t &zi) {
+    // offset nibbles u = n + 8 as 1024 + u in f16, then minus 1032: exact
+    const uint32_t t = p ^ 0x88888888u;
+    const uint32_t lo = t & 0x0f0f0f0fu, hi = (t >> 4) & 0x0f0f0f0fu;
+    h8_t a;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t bits =
+            __builtin_amdgcn_perm(hi, lo, (uint32_t)i | 0x0c00u | (uint32_t)(i + 4) << 16 | 0x0c000000u) | 0x64006400u;
+        const h2_t v = __builtin_bit_cast(h2_t, bits) - h2_t{(_Float16)1032.0f, (_Float16)1032.0f};
+        a[2 * i] = v[0];
+        a[2 * i + 1] = v[1];
+    }
+    const f4_t zero = {0.0f, 0.0f, 0.0f, 0.0f};
+    f4_t yr = mfma_h(a, k.dl[0], zero), yi = mfma_h(a, k.dl[1], zero);
+    yr = mfma_h(a, k.dh[0], yr);
+    yi = mfma_h(a, k.dh[1], yi);
+    h8_t bh, bl;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float2 y = cmul(make_float2(yr[i], yi[i]), k.w[i]);
+        // hi: y cut to 11 significant bits (exact in f16 down to 2^-14;
+        // below that its conversion rounds by at most 2^-25), lo = y - hi
+        // (exact in f32) rounded to f16
+        const float hr = __uint_as_float(__float_as_uint(y.x) & 0xffffe000u);
+        const float hm = __uint_as_float(__float_as_uint(y.y) & 0xffffe000u);
+        bh[2 * i] = (_Float16)hr;
+        bh[2 * i + 1] = (_Float16)hm;
+        bl[2 * i] = (_Float16)(y.x - hr);
+        bl[2 * i + 1] = (_Float16)(y.y - hm);
+    }
+    zr = mfma_h(k.dl[0], bh, zero);
+    zi = mfma_h(k.dl[1], bh, zero);
+    zr = mfma_h(k.dh[0], bl, zr);
+    zi = mfma_h(k.dh[1], bl, zi);
+    zr = mfma_h(k.dh[0], bh, zr);
+    zi = mfma_h(k.dh[1], bh, zi);
+}
+
+// The wavefront's T transforms of a round: bytes from the staging bb (dword
+// d of a block at (d mod M/64) 16 + d div M/64, so that lane (j, g) finds the
+// bytes it needs, z[16 s + j] (256) or z[32 s + 2j + p] (512) for s = 4g ..
+// 4g + 3, at one byte of four consecutive dwords) to Z in slot z[t].  All
+// reads come first and all writes last, so the transforms' products and
+// vector work interleave.
+template <int M, int T>
+__device__ __forceinline__ void fft_mfma(const uint32_t *bb, float2 *const (&z)[T], const MfmaFft<M> &k) {
+    constexpr int P = MfmaFft<M>::P;
+    const int lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
+    uint4 w[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+        w[t] = *reinterpret_cast<const uint4 *>(bb + t * (M / 4) + (j / (64 / (M / 16))) * 16 + 4 * g);
+    f4_t zr[T][P], zi[T][P];
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const uint32_t b = __builtin_amdgcn_perm(w[t].y, w[t].x, k.sel01[p]) |
+                               __builtin_amdgcn_perm(w[t].w, w[t].z, k.sel23[p]);
+            dft256_mfma<M>(b, k, zr[t][p], zi[t][p]);
+        }
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        if (z[t] == nullptr) continue;  // idle slot (wave-uniform)
+        if constexpr (P == 1) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) z[t][pad(j + 16 * (4 * g + i))] = make_float2(zr[t][0][i], zi[t][0][i]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int q = j + 16 * (4 * g + i);
+                const float2 e = make_float2(zr[t][0][i], zi[t][0][i]);
+                const float2 o = cmul(make_float2(zr[t][1][i], zi[t][1][i]), k.w2[i]);
+                z[t][pad(q)] = cadd(e, o);
+                z[t][pad(q + 256)] = csub(e, o);
+            }
+        }
+    }
+}
+
+// The per-lane constants of a transform of M points for records of PREC.
+template <int M, int PREC>
+using FftConsts = typename std::conditional<mfma_fft<M, PREC>(), MfmaFft<M>, PassTw<M>>::type;
+
 // Signed nibble at bit offset `off` of w.
 __device__ __forceinline__ float nib(uint32_t w, int off) {
     return (float)((int)(w << (28 - off)) >> 28);
+}
+
+// Adds to wsat (wave-uniform) the number of the wavefront's values v with
+// |v| >= lim.  The exact count runs only when some lane's largest |v| reaches
+// lim, which saturation makes rare: otherwise a running maximum is all.
+template <int NV>
+__device__ __forceinline__ void count_saturated(const float (&v)[NV], float lim, unsigned &wsat) {
+    float m = 0.0f;
+#pragma unroll
+    for (int t = 0; t < NV; t += 2) m = fmaxf(m, fmaxf(fabsf(v[t]), fabsf(v[t + 1])));
+    if (__ballot(m >= lim)) {
+#pragma unroll
+        for (int t = 0; t < NV; ++t) wsat += (unsigned)__popcll(__ballot(fabsf(v[t]) >= lim));
+    }
 }
 
 // Pack TS spectra of one (channel, antenna) into a 16-byte record
@@ -220,11 +399,13 @@ __device__ __forceinline__ uint4 make_record(const float *re, const float *im, f
         // Record: [h of re x4][h of im x4][l of re x4][l of im x4].
         constexpr float kMagic = 12582912.0f;
         uint32_t hb[8], lb[8];
+        float v[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) v[t] = (t < 4 ? re[t] : im[t - 4]) * sc;
+        count_saturated<8>(v, (float)kI16Max + 0.5f, wsat);
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
-            const float v = (t < 4 ? re[t] : im[t - 4]) * sc;
-            wsat += (unsigned)__popcll(__ballot(fabsf(v) >= (float)kI16Max + 0.5f));
-            const float qm = __builtin_amdgcn_fmed3f(v, -(float)kI16Max, (float)kI16Max) + kMagic;
+            const float qm = __builtin_amdgcn_fmed3f(v[t], -(float)kI16Max, (float)kI16Max) + kMagic;
             const float hm = fmaf(qm - kMagic, 1.0f / 255.0f, kMagic);
             hb[t] = __float_as_uint(hm);
             lb[t] = __float_as_uint(qm) + __float_as_uint(hm);
@@ -243,17 +424,17 @@ __device__ __forceinline__ uint4 make_record(const float *re, const float *im, f
         // rint and the clamp to +-127 commute, so clamp first; adding 1.5 * 2^23
         // then rounds to the nearest integer (ties to even) and leaves it, as
         // two's complement, in the low byte of the sum
+        float v[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) v[t] = (t < 8 ? re[t] : im[t - 8]) * sc;
+        count_saturated<16>(v, 127.5f, wsat);
         uint32_t w[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const float *x = k < 2 ? re + 4 * k : im + 4 * (k - 2);
             uint32_t b[4];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const float v = x[t] * sc;
-                wsat += (unsigned)__popcll(__ballot(fabsf(v) >= 127.5f));
-                b[t] = __float_as_uint(__builtin_amdgcn_fmed3f(v, -127.0f, 127.0f) + 12582912.0f);
-            }
+            for (int t = 0; t < 4; ++t)
+                b[t] = __float_as_uint(__builtin_amdgcn_fmed3f(v[4 * k + t], -127.0f, 127.0f) + 12582912.0f);
             // low bytes of b[0..3] -> bytes 0..3 of the word
             w[k] = __builtin_amdgcn_perm(b[1], b[0], 0x0c0c0400u) | __builtin_amdgcn_perm(b[3], b[2], 0x04000c0cu);
         }
@@ -326,54 +507,76 @@ __device__ __forceinline__ void load_tile(const FArgs &args, int tq, int g, u32x
 
 // Transform the NF blocks of a tile, loaded by load_tile, into zbuf slots
 // (ts * GA + ga).
-template <int M, int NF, int ROUNDS>
+template <int M, int PREC, int NF, int ROUNDS>
 __device__ __forceinline__ void tile_ffts(const u32x4 (&raw)[ROUNDS], float2 *zbuf, uint32_t *bbuf,
-                                          const PassTw<M> &tw) {
+                                          const FftConsts<M, PREC> &tw) {
     constexpr int L = M / 16, FPR = kThreads / L, SLOT = M + M / 16 + 1;
     const int fs = threadIdx.x / L, j = threadIdx.x % L;
     uint32_t *bb = bbuf + fs * (M / 4);
+    // dword d of the block goes to (d mod L/4)*16 + d div L/4, so the 16
+    // dwords pass 1 needs in a lane are contiguous
+    auto stage = [&](const u32x4 &raw_r) {
+        const uint32_t w[4] = {raw_r[0], raw_r[1], raw_r[2], raw_r[3]};
 #pragma unroll
-    for (int r = 0; r < ROUNDS; ++r) {
-        const int fi = r * FPR + fs;
-        if (NF < FPR && fi >= NF) break;  // idle transform slots (one round only)
-        float2 *z = zbuf + fi * SLOT;
-        // dword d of the block goes to (d mod L/4)*16 + d div L/4, so the 16
-        // dwords pass 1 needs in a lane are contiguous
-        {
-            const uint32_t w[4] = {raw[r][0], raw[r][1], raw[r][2], raw[r][3]};
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int d = 4 * j + c;
-                bb[(d % (L / 4)) * 16 + d / (L / 4)] = w[c];
-            }
+        for (int c = 0; c < 4; ++c) {
+            const int d = 4 * j + c;
+            bb[(d % (L / 4)) * 16 + d / (L / 4)] = w[c];
         }
-        wave_lds_sync();
-        // pass 1: radix 16 over z[j + r L], unpacked from the bytes
-        {
-            float2 v[16];
-            const uint4 *src = reinterpret_cast<const uint4 *>(bb + (j / 4) * 16);
-            const int off = 8 * (j & 3);
+    };
+    if constexpr (mfma_fft<M, PREC>()) {
+        // Every lane takes part (the matrix products need the whole
+        // wavefront): the bytes of idle slots are the zero page's, and the
+        // wavefront runs its own slots of the round one at a time.
+        constexpr int W = 64 / L;
+        const int f0 = (threadIdx.x >> 6) * W;
 #pragma unroll
-            for (int q4 = 0; q4 < 4; ++q4) {
-                const uint4 w4 = src[q4];
-                const uint32_t w[4] = {w4.x, w4.y, w4.z, w4.w};
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const uint32_t byte = w[c] >> off;
-                    v[4 * q4 + c] = make_float2(nib(byte, 0), nib(byte, 4));
-                }
-            }
-            dft16(v);
-#pragma unroll
-            for (int q = 0; q < 16; ++q) z[pad(16 * j + q)] = v[q];
-        }
-        wave_lds_sync();
-        fft_pass<M, PassTw<M>::R2>(z, j, 16, tw.w2);
-        if constexpr (PassTw<M>::R3 > 1) {
+        for (int r = 0; r < ROUNDS; ++r) {
+            stage(raw[r]);
             wave_lds_sync();
-            fft_pass<M, PassTw<M>::R3>(z, j, 256, tw.w3);
+            float2 *z[W];
+#pragma unroll
+            for (int t = 0; t < W; ++t) {
+                const int ft = r * FPR + f0 + t;
+                z[t] = (NF % FPR == 0 || ft < NF) ? zbuf + ft * SLOT : nullptr;
+            }
+            fft_mfma<M, W>(bbuf + f0 * (M / 4), z, tw);
+            wave_lds_sync();
         }
-        wave_lds_sync();
+    } else {
+#pragma unroll
+        for (int r = 0; r < ROUNDS; ++r) {
+            const int fi = r * FPR + fs;
+            if (NF < FPR && fi >= NF) break;  // idle transform slots (one round only)
+            float2 *z = zbuf + fi * SLOT;
+            stage(raw[r]);
+            wave_lds_sync();
+            // pass 1: radix 16 over z[j + r L], unpacked from the bytes
+            {
+                float2 v[16];
+                const uint4 *src = reinterpret_cast<const uint4 *>(bb + (j / 4) * 16);
+                const int off = 8 * (j & 3);
+#pragma unroll
+                for (int q4 = 0; q4 < 4; ++q4) {
+                    const uint4 w4 = src[q4];
+                    const uint32_t w[4] = {w4.x, w4.y, w4.z, w4.w};
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const uint32_t byte = w[c] >> off;
+                        v[4 * q4 + c] = make_float2(nib(byte, 0), nib(byte, 4));
+                    }
+                }
+                dft16(v);
+#pragma unroll
+                for (int q = 0; q < 16; ++q) z[pad(16 * j + q)] = v[q];
+            }
+            wave_lds_sync();
+            fft_pass<M, PassTw<M>::R2>(z, j, 16, tw.w2);
+            if constexpr (PassTw<M>::R3 > 1) {
+                wave_lds_sync();
+                fft_pass<M, PassTw<M>::R3>(z, j, 256, tw.w3);
+            }
+            wave_lds_sync();
+        }
     }
 }
 
@@ -382,7 +585,7 @@ __device__ __forceinline__ void tile_ffts(const u32x4 (&raw)[ROUNDS], float2 *zb
 template <int M, int PREC, int GA>
 struct TileConsts {
     using Sh = FShape<M, PREC, GA, false>;
-    PassTw<M> ptw;
+    FftConsts<M, PREC> ptw;
     float2 bw[Sh::TPT];
     __device__ __forceinline__ void load(const FArgs &args) {
         const int tid = threadIdx.x;
@@ -477,7 +680,7 @@ __device__ __forceinline__ void tile_records(const FArgs &args, int tq, int g,
     const uint32_t span = (uint32_t)M * kTQB * (uint32_t)args.a_pad * kRecordBytes;
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         args.spec + (int64_t)tqb * M * kTQB * args.a_pad, 0, (int)span, kBufferRsrcFlags);
-    tile_ffts<M, Sh::NF, Sh::ROUNDS>(cur, zbuf, bbuf, k.ptw);
+    tile_ffts<M, PREC, Sh::NF, Sh::ROUNDS>(cur, zbuf, bbuf, k.ptw);
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < TPT; ++it) {
@@ -619,7 +822,7 @@ __device__ __forceinline__ void f_power_block(const FArgs &args, int blk, float2
     if (pg >= args.ngroups) return;
     const int tile0 = pw * args.tiles_per_wg;
     const int tile1 = min(tile0 + args.tiles_per_wg, args.ntq);
-    PassTw<M> ptw;
+    FftConsts<M, kFP32> ptw;
     ptw.load(tid % (M / 16), args.tw);
     float2 bw[TPT];
     float plo[TPT], phi[TPT];
@@ -632,7 +835,7 @@ __device__ __forceinline__ void f_power_block(const FArgs &args, int blk, float2
     for (int tq = tile0; tq < tile1; ++tq) {
         u32x4 raw[ROUNDS];
         load_tile<M, GA, TS, NF, ROUNDS>(args, tq, pg, raw);
-        tile_ffts<M, NF, ROUNDS>(raw, zbuf, bbuf, ptw);
+        tile_ffts<M, kFP32, NF, ROUNDS>(raw, zbuf, bbuf, ptw);
         __syncthreads();
 #pragma unroll
         for (int it = 0; it < TPT; ++it) {
