@@ -452,6 +452,8 @@ def main():
     ap.add_argument("--cpu-spectra-one-thread", type=int, default=4096)
     ap.add_argument("--cpu-spectra-large-n", type=int, default=1024)
     ap.add_argument("--forms", default="fp32,fp16,int8,int16")
+    ap.add_argument("--pipeline", default="tuned", choices=("tuned", "staged", "fused"),
+                    help="the pipeline of every form: the autotuner's choice, or one for all (counter runs)")
     ap.add_argument("--no-extra", action="store_true", help="skip every workload beyond the headline step")
     ap.add_argument("--legs", default="fused,tracking,ingest,large_n,batch",
                     help="extra workloads to run after the headline step (comma list)")
@@ -482,7 +484,8 @@ def main():
     xops_per_int = metrics.x_ops(N_ANT, K, S_INT)
     forms = {}
     for name in args.forms.split(","):
-        ms, wall_ms, stats, tiles = run_form(corr, torch, name, inputs, args.steps, args.warmup, timing=True)
+        ms, wall_ms, stats, tiles = run_form(corr, torch, name, inputs, args.steps, args.warmup, timing=True,
+                                             pipeline=None if args.pipeline == "tuned" else args.pipeline)
         n_int = args.steps * N_INT
         x_ms = stats["ms_x"] / n_int
         f_ms = stats["ms_f"] / n_int
