@@ -113,20 +113,26 @@ int corr_get_tiles(corr_handle h, corr_tiles *t);
  *     buffers small enough to stay in the caches; the others are X workers
  *     whose accumulators stay in registers across all chunks and are written
  *     out once (float forms: every 2048 (FP32) / 16384 (FP16) spectra of a
- *     partial); one dump follows.  f_workgroups_per_cu: workgroups per CU that
- *     run the F-stage (the rest of the CU's resident workgroups run X).
+ *     partial); one dump follows.  Two layouts of the roles:
+ *       mixed (f_cus_per_xcd = 0): every CU runs f_workgroups_per_cu F
+ *         workgroups and its other resident workgroups run X;
+ *       split (f_cus_per_xcd > 0): the first f_cus_per_xcd CUs of each XCD
+ *         run only F workgroups and the other CUs only X workgroups
+ *         (f_workgroups_per_cu must then be 0; at most CUs per XCD - 1).
  *     FP32, FP16 and INT8 with N <= 48; no delay / phase tracking; not in
  *     batches.  Results: INT8 identical to the staged pipeline, FP32 / FP16
  *     within their tolerance.
  * 0 for chunk_spectra (a multiple of 64), ring_slots (1..8) or
- * f_workgroups_per_cu picks a default.  Before the first process call only
+ * f_workgroups_per_cu picks a default; 0 for f_cus_per_xcd is the mixed
+ * layout.  Both layout arguments non-zero: CORR_EINVAL.  Before the first process call only
  * (CORR_ESTATE after); a shape or precision the fused kernel does not cover
  * fails the first process call (and corr_get_tiles) with CORR_EINVAL.  With
  * FUSED, corr_get_tiles reports chunk_spectra, the partials per channel in
  * x_splits and the F group.  */
 #define CORR_PIPELINE_STAGED 0
 #define CORR_PIPELINE_FUSED 1
-int corr_set_pipeline(corr_handle h, int pipeline, int chunk_spectra, int ring_slots, int f_workgroups_per_cu);
+int corr_set_pipeline(corr_handle h, int pipeline, int chunk_spectra, int ring_slots, int f_workgroups_per_cu,
+                      int f_cus_per_xcd);
 
 /* Correlate one integration.  packed_samples: DEVICE pointer to
  * n_spectra*N*K bytes in the frame layout above.  Enqueues the whole F + X +

@@ -114,7 +114,7 @@ def load(path: str = LIB_PATH):
         "corr_batch_read_cps_raw": (I, [P, I, P]),
         "corr_batch_read_scales": (I, [P, I, P]),
         "corr_process_noalloc": (I, [I, I, I, I, P, P, P, P]),
-        "corr_set_pipeline": (I, [P, I, I, I, I]),
+        "corr_set_pipeline": (I, [P, I, I, I, I, I]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -187,8 +187,10 @@ def corr_get_tiles(h) -> dict:
     return {"chunk_spectra": t.chunk_spectra, "x_splits": t.x_splits, "f_group": t.f_group}
 
 
-def corr_set_pipeline(h, pipeline: int, chunk_spectra: int = 0, ring_slots: int = 0, f_workgroups_per_cu: int = 0):
-    return _check(load().corr_set_pipeline(h, pipeline, chunk_spectra, ring_slots, f_workgroups_per_cu))
+def corr_set_pipeline(h, pipeline: int, chunk_spectra: int = 0, ring_slots: int = 0, f_workgroups_per_cu: int = 0,
+                      f_cus_per_xcd: int = 0):
+    return _check(load().corr_set_pipeline(h, pipeline, chunk_spectra, ring_slots, f_workgroups_per_cu,
+                                           f_cus_per_xcd))
 
 
 def corr_process(h, packed_ptr: int, stream: int = 0):
@@ -303,8 +305,8 @@ class Correlator:
         pipeline: None (with tiles="auto": the pipeline the autotuner found
         faster for this shape, else staged), "staged", or "fused" optionally
         with its parameters as a dict {"chunk_spectra", "ring_slots",
-        "f_workgroups_per_cu"} (with tiles="auto", the autotuner's fused entry
-        when it has one). A fused pipeline that only the autotuner chose gives
+        "f_workgroups_per_cu", "f_cus_per_xcd"} (with tiles="auto", the
+        autotuner's fused entry when it has one). A fused pipeline that only the autotuner chose gives
         way to the staged one with its tuned tiles when tracking is switched
         on before the first process() (the fused kernel does not track)."""
         self.N, self.K, self.S = N, K, n_spectra
@@ -330,8 +332,8 @@ class Correlator:
                 if not params and isinstance(tiles, str) and tiles == "auto":
                     from . import tune
                     found = tune.lookup(N, K, n_spectra, name, mode="fused")
-                    params = {k: found[k] for k in ("chunk_spectra", "ring_slots", "f_workgroups_per_cu")} \
-                        if found else {}
+                    params = {k: found[k] for k in ("chunk_spectra", "ring_slots", "f_workgroups_per_cu",
+                                                    "f_cus_per_xcd") if k in found} if found else {}
                 corr_set_pipeline(self.h, CORR_PIPELINE_FUSED, **params)
                 if chosen:
                     self._staged_fallback = {k: staged[k] for k in ("chunk_spectra", "x_splits", "f_group")} \

@@ -220,8 +220,11 @@ struct FxArgs {
     int nchunks;
     int ring;            // slots in the ring
     int64_t slot_recs;   // records (uint4) per slot
-    int n_fwg;           // workgroups [0, n_fwg) run the F-stage
+    int n_fwg;           // workgroups that run the F-stage
     int flush_chunks;    // X units start a new partial every this many chunks
+    int cus;             // CUs of the device (workgroup b runs on CU slot b mod cus)
+    int f_cus;           // 0: workgroups [0, n_fwg) run F on every CU; else the
+                         // first f_cus CUs of each XCD run only F, the rest only X
 };
 // Counter words: per chunk c from kFxHdr + c kFxPerChunk: the eight per-XCD
 // tile tickets, the eight per-XCD counts of F workgroups that finished the

@@ -9,7 +9,10 @@
 // workgroup's progress always ends.  A cooperative launch places workgroup b
 // on XCD b % 8 and fills the CUs breadth first (b and b + #CUs share a CU),
 // so workgroups [0, n_fwg) with n_fwg a multiple of the CU count give every
-// CU the same mix of F and X workgroups.
+// CU the same mix of F and X workgroups (mixed layout).  In the split layout
+// the roles go by CU instead: CU slot p = b mod #CUs is CU p / 8 of XCD p % 8,
+// and the first f_cus CUs of every XCD run only F workgroups, the others only
+// X workgroups, which then keep several X waves per SIMD.
 //
 //   F workgroups: for chunk c = 0, 1, ... take the chunk's tiles one ticket at
 //     a time (per-XCD counters, as the standalone F-stage), writing records
@@ -111,10 +114,10 @@ __device__ __forceinline__ void fx_f_role(const FxArgs &a, float2 *zbuf, uint32_
 }
 
 template <int PREC, int RB>
-__device__ __forceinline__ void fx_x_role(const FxArgs &a, float *tb) {
+__device__ __forceinline__ void fx_x_role(const FxArgs &a, int xrank, float *tb) {
     const int tg = record_times(PREC);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int unit = (blockIdx.x - a.n_fwg) * 4 + w;
+    const int unit = xrank * 4 + w;
     const bool active = unit < a.x.K * a.x.nsplit;
     const int f = unit % a.x.K, sp = unit / a.x.K;
     XRegion<PREC, RB, true> acc;
@@ -161,11 +164,22 @@ __global__ __launch_bounds__(kThreads, fx_min_blocks(M, PREC)) void fx_kernel(Fx
     __shared__ __attribute__((aligned(16))) uint32_t bbuf[Sh::FPR * (M / 4)];
     __shared__ int s_tk[2];
     const FxArgs &a = kargs;
-    if ((int)blockIdx.x < a.n_fwg) {
+    const int b = blockIdx.x;
+    bool f_role;
+    int xrank;  // this workgroup's index among the X workgroups
+    if (a.f_cus) {
+        const int p = b % a.cus, nf = 8 * a.f_cus;
+        f_role = p < nf;
+        xrank = (b / a.cus) * (a.cus - nf) + (p - nf);
+    } else {
+        f_role = b < a.n_fwg;
+        xrank = b - a.n_fwg;
+    }
+    if (f_role) {
         fx_f_role<M, PREC, GA>(a, zbuf, bbuf, s_tk);
     } else {
         float *tb = reinterpret_cast<float *>(zbuf) + (threadIdx.x >> 6) * 16 * 17;
-        fx_x_role<PREC, RB>(a, tb);
+        fx_x_role<PREC, RB>(a, xrank, tb);
     }
 }
 

@@ -157,7 +157,7 @@ struct corr_ctx {
     // period, chunks, partial slots, records per ring slot; counters and the
     // sticky error flag
     int pipeline = CORR_PIPELINE_STAGED;
-    int fx_chunk = 0, fx_ring = 0, fx_fpc = 0;
+    int fx_chunk = 0, fx_ring = 0, fx_fpc = 0, fx_fcus = 0, fx_cus = 0;
     int fx_grid = 0, fx_nfwg = 0, fx_nsplit = 0, fx_flush = 0, fx_nchunks = 0, fx_nslots = 0;
     int64_t fx_slot_recs = 0;
     unsigned *fx_ctr = nullptr;
@@ -273,12 +273,23 @@ int plan_fused(corr_ctx *h) {
     // workgroup b runs on XCD b mod 8 (gfx950: 8 XCDs of 32 CUs), and each
     // XCD's F workgroups publish through that XCD's L2
     if (cus % 8) return fail(CORR_EINVAL, "the fused pipeline expects the CUs in 8 XCDs (%d CUs)", cus);
-    const int fpc = h->fx_fpc ? h->fx_fpc : per_cu - 1;
-    if (fpc < 1 || fpc >= per_cu)
-        return fail(CORR_EINVAL, "f_workgroups_per_cu=%d out of [1, %d] (%d workgroups per CU)", fpc, per_cu - 1, per_cu);
     h->fx_grid = per_cu * cus;
-    h->fx_nfwg = fpc * cus;
-    const int x_waves = 4 * (per_cu - fpc) * cus;
+    h->fx_cus = cus;
+    int x_waves = 0;
+    if (h->fx_fcus) {
+        // split layout: whole CUs per role, f_cus of each XCD's CUs run F
+        if (h->fx_fcus >= cus / 8)
+            return fail(CORR_EINVAL, "f_cus_per_xcd=%d out of [1, %d] (%d CUs per XCD)", h->fx_fcus, cus / 8 - 1, cus / 8);
+        h->fx_nfwg = 8 * h->fx_fcus * per_cu;
+        x_waves = 4 * (cus - 8 * h->fx_fcus) * per_cu;
+    } else {
+        const int fpc = h->fx_fpc ? h->fx_fpc : per_cu - 1;
+        if (fpc < 1 || fpc >= per_cu)
+            return fail(CORR_EINVAL, "f_workgroups_per_cu=%d out of [1, %d] (%d workgroups per CU)", fpc, per_cu - 1,
+                        per_cu);
+        h->fx_nfwg = fpc * cus;
+        x_waves = 4 * (per_cu - fpc) * cus;
+    }
     h->fx_nsplit = std::max(1, std::min(64, x_waves / h->K));
     if (h->K > x_waves) return fail(CORR_EINVAL, "the fused pipeline needs %d X waves for K=%d, has %d", h->K, h->K, x_waves);
     // chunks: records of a slot about 72 MB, so a ring of three stays in the
@@ -529,6 +540,8 @@ int process_one(corr_ctx *h, const uint8_t *in, hipStream_t st) {
         fx.ring = h->fx_ring;
         fx.slot_recs = h->fx_slot_recs;
         fx.n_fwg = h->fx_nfwg;
+        fx.cus = h->fx_cus;
+        fx.f_cus = h->fx_fcus;
         fx.flush_chunks = h->fx_flush;
         HIP_TRY(launch_fill_zero(h->fx_ctr, h->fx_ctr_bytes, st), "fused counter clear");
         timer_begin(h, 4, st);
@@ -743,7 +756,8 @@ int corr_get_tiles(corr_handle hh, corr_tiles *t) {
     return CORR_OK;
 }
 
-int corr_set_pipeline(corr_handle hh, int pipeline, int chunk_spectra, int ring_slots, int f_workgroups_per_cu) {
+int corr_set_pipeline(corr_handle hh, int pipeline, int chunk_spectra, int ring_slots, int f_workgroups_per_cu,
+                      int f_cus_per_xcd) {
     corr_ctx *h = single(hh);
     if (!h) return fail(CORR_EINVAL, "invalid handle");
     if (pipeline != CORR_PIPELINE_STAGED && pipeline != CORR_PIPELINE_FUSED)
@@ -753,11 +767,16 @@ int corr_set_pipeline(corr_handle hh, int pipeline, int chunk_spectra, int ring_
     if (ring_slots < 0 || ring_slots > 8) return fail(CORR_EINVAL, "ring_slots=%d out of [0, 8]", ring_slots);
     if (f_workgroups_per_cu < 0 || f_workgroups_per_cu > 16)
         return fail(CORR_EINVAL, "f_workgroups_per_cu=%d out of [0, 16]", f_workgroups_per_cu);
+    if (f_cus_per_xcd < 0 || f_cus_per_xcd > 64)
+        return fail(CORR_EINVAL, "f_cus_per_xcd=%d out of [0, 64]", f_cus_per_xcd);
+    if (f_workgroups_per_cu && f_cus_per_xcd)
+        return fail(CORR_EINVAL, "f_workgroups_per_cu and f_cus_per_xcd select different layouts; set one");
     if (h->started || h->planned) return fail(CORR_ESTATE, "the pipeline is fixed once processing has started");
     h->pipeline = pipeline;
     h->fx_chunk = chunk_spectra;
     h->fx_ring = ring_slots;
     h->fx_fpc = f_workgroups_per_cu;
+    h->fx_fcus = f_cus_per_xcd;
     return CORR_OK;
 }
 

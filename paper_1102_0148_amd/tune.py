@@ -156,16 +156,18 @@ def tune_single(N: int, K: int, S: int, prec: str, log=print) -> Tuple[dict, flo
 
 def fused_candidates(N: int, K: int, S: int, prec: str) -> List[dict]:
     """Fused-pipeline choices: ring slots of about 24 to 96 MB of records,
-    two or three slots, the default or one F workgroup per CU.  The fused
-    kernel covers fp32, fp16 and int8 at N <= 48."""
+    two or three slots, and the role layout: mixed with the default or one F
+    workgroup per CU, or split with 12 to 24 of each XCD's 32 CUs on F.  The
+    fused kernel covers fp32, fp16 and int8 at N <= 48."""
     if prec not in ("fp32", "fp16", "int8") or N > 48:
         return []
     a_pad = 16 * ((N + 15) // 16)
     per_spectrum = a_pad * K * 16 // record_times(prec)
     whole = (S + 63) // 64 * 64
     chunks = sorted({min(whole, max(64, (mb << 20) // per_spectrum // 64 * 64)) for mb in (24, 48, 72, 96)})
-    return [{"chunk_spectra": c, "ring_slots": r, "f_workgroups_per_cu": f}
-            for c in chunks for r in (2, 3) for f in (0, 1)]
+    layouts = [{"f_workgroups_per_cu": f, "f_cus_per_xcd": 0} for f in (0, 1)] + \
+              [{"f_workgroups_per_cu": 0, "f_cus_per_xcd": n} for n in (12, 16, 20, 24)]
+    return [dict(chunk_spectra=c, ring_slots=r, **l) for c in chunks for r in (2, 3) for l in layouts]
 
 
 def _time_e2e(corr, torch, N, K, S, prec, x, tiles=None, pipeline=None, reps=4, warm=1) -> float:

@@ -26,19 +26,22 @@ def _fused(N, K, S, prec, packed, **params):
     return c
 
 
-# (N, K, S, chunk, ring, f per CU): several chunks with a ragged last one,
-# ring depths 1-3, one and two antenna blocks (N = 8, 20) and three (N = 44)
-CASES = [(44, 256, 3000, 512, 3, 0), (44, 256, 1000, 256, 1, 0), (20, 512, 700, 128, 2, 0),
-         (8, 128, 2500, 1024, 2, 0), (44, 1024, 300, 64, 3, 0), (33, 256, 1200, 384, 2, 1)]
+# (N, K, S, chunk, ring, F workgroups per CU, F CUs per XCD): several chunks
+# with a ragged last one, ring depths 1-3, one and two antenna blocks (N = 8,
+# 20) and three (N = 44); the mixed role layout and the split one
+CASES = [(44, 256, 3000, 512, 3, 0, 0), (44, 256, 1000, 256, 1, 0, 0), (20, 512, 700, 128, 2, 0, 0),
+         (8, 128, 2500, 1024, 2, 0, 0), (44, 1024, 300, 64, 3, 0, 0), (33, 256, 1200, 384, 2, 1, 0),
+         (44, 256, 3000, 512, 3, 0, 12), (20, 512, 1100, 256, 2, 0, 4), (8, 128, 700, 64, 1, 0, 20)]
 
 
-@pytest.mark.parametrize("N,K,S,chunk,ring,fpc", CASES)
+@pytest.mark.parametrize("N,K,S,chunk,ring,fpc,fcus", CASES)
 @pytest.mark.parametrize("prec", ["fp32", "fp16", "int8"])
-def test_fused_matches_oracle_and_staged(prec, N, K, S, chunk, ring, fpc):
-    print(f"\n[fused] {prec} N={N} K={K} S={S} chunk={chunk} ring={ring} fpc={fpc}", flush=True)
+def test_fused_matches_oracle_and_staged(prec, N, K, S, chunk, ring, fpc, fcus):
+    print(f"\n[fused] {prec} N={N} K={K} S={S} chunk={chunk} ring={ring} fpc={fpc} fcus={fcus}", flush=True)
     packed = _packed(N, K, S, seed=N + K + S, tone=prec != "fp32")
     x = packed.cuda()
-    c = _fused(N, K, S, prec, x, chunk_spectra=chunk, ring_slots=ring, f_workgroups_per_cu=fpc)
+    c = _fused(N, K, S, prec, x, chunk_spectra=chunk, ring_slots=ring, f_workgroups_per_cu=fpc,
+               f_cus_per_xcd=fcus)
     print(f"  tiles {c.tiles()}", flush=True)
     raw = c.read_cps_raw()
     if prec == "int8":
@@ -118,6 +121,15 @@ def test_fused_refuses_what_it_does_not_cover():
     assert e.value.code == corr.CORR_ESTATE
     with pytest.raises(corr.CorrError) as e:
         corr.corr_set_pipeline(c.h, 5)
+    assert e.value.code == corr.CORR_EINVAL
+    # both role layouts at once, and a split that leaves no X CUs
+    c = corr.Correlator(8, 256, 64)
+    with pytest.raises(corr.CorrError) as e:
+        corr.corr_set_pipeline(c.h, corr.CORR_PIPELINE_FUSED, 0, 0, 1, 4)
+    assert e.value.code == corr.CORR_EINVAL
+    c = corr.Correlator(8, 256, 64, pipeline={"f_cus_per_xcd": 32})
+    with pytest.raises(corr.CorrError) as e:
+        c.process(x[: 64 * 8 * 256])
     assert e.value.code == corr.CORR_EINVAL
 
 

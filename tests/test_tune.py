@@ -45,3 +45,16 @@ def test_keys_per_batch_mode():
     assert tune.key(8, 128, 100, "int8", batch="persistent") == "gfx950:N=8:K=128:S=100:int8:batch"
     assert tune.key(8, 128, 100, "int8", batch="branches") == "gfx950:N=8:K=128:S=100:int8:branches"
 
+
+
+def test_fused_candidates_one_layout_each():
+    """Every fused candidate names one role layout (the library refuses both
+    at once), chunks stay within the integration, and shapes the fused
+    kernel does not cover get none."""
+    c = tune.fused_candidates(44, 256, 65536, "fp32")
+    assert c and all((x["f_workgroups_per_cu"] == 0) or (x["f_cus_per_xcd"] == 0) for x in c)
+    assert {x["f_cus_per_xcd"] for x in c} == {0, 12, 16, 20, 24}
+    assert all(64 <= x["chunk_spectra"] <= 65536 and x["chunk_spectra"] % 64 == 0 for x in c)
+    assert tune.fused_candidates(44, 256, 1000, "int8")[0]["chunk_spectra"] <= 1024
+    assert tune.fused_candidates(44, 256, 65536, "int16") == []
+    assert tune.fused_candidates(64, 256, 65536, "fp32") == []
