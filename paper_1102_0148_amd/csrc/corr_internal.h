@@ -197,6 +197,9 @@ hipError_t launch_xstage(int prec, int rb, int kind, const XArgs &a, hipStream_t
 // int8 / fp16 with 4 x 4-block regions: one workgroup per (group, channel,
 // split), the group's blocks staged through an LDS ring (a.groups).
 hipError_t launch_xgroups(int prec, const XArgs &a, hipStream_t st);
+// int8 / fp16 with 4 x 4-block regions in exactly 4 region rows (16 blocks):
+// one workgroup per (channel, split) stages all 16 blocks of a k-block.
+hipError_t launch_xchan(int prec, const XArgs &a, hipStream_t st);
 // int16 (also reached through launch_xstage): rb <= 3 diagonal, rb <= 2 off
 // the diagonal; a.nkb even; partials are double2 (exact integers).
 hipError_t launch_xstage16(int rb, int kind, const XArgs &a, hipStream_t st);

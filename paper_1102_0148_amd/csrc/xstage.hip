@@ -114,7 +114,49 @@ hipError_t launch_group(const XArgs &a, hipStream_t st) {
     return hipGetLastError();
 }
 
+// Whole-channel groups (16 antenna blocks): eight waves per workgroup, one
+// workgroup per (channel, split), the 16 blocks of a k-block staged once.
+template <int PREC>
+__global__ __launch_bounds__(kXChanWaves * 64, 1) void xchan_kernel(XArgs a) {
+    __shared__ __attribute__((aligned(16))) uint4 st0[kXStage];
+    __shared__ __attribute__((aligned(16))) uint4 st1[kXStage];
+    __shared__ __attribute__((aligned(16))) uint4 st2[kXStage];
+#if X_RING >= 4
+    __shared__ __attribute__((aligned(16))) uint4 st3[kXStage];
+#endif
+#if X_RING >= 5
+    __shared__ __attribute__((aligned(16))) uint4 st4[kXStage];
+#endif
+    uint4 *const st[kXRing] = {st0, st1, st2
+#if X_RING >= 4
+                               , st3
+#endif
+#if X_RING >= 5
+                               , st4
+#endif
+    };
+    // logical workgroup as in xstage_kernel: neighbouring channels share an XCD
+    const int lb = (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+    x_chan<PREC>(a, lb, st);
+}
+
+template <int PREC>
+hipError_t launch_chan(const XArgs &a, hipStream_t st) {
+    const int64_t units = (int64_t)a.K * a.nsplit;
+    const int grid = (int)(8 * ((units + 7) / 8));  // a multiple of 8; units past the end exit
+    hipLaunchKernelGGL((xchan_kernel<PREC>), dim3(grid), dim3(kXChanWaves * 64), 0, st, a);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_xchan(int prec, const XArgs &a, hipStream_t st) {
+    switch (prec) {
+        case kFP16: return launch_chan<kFP16>(a, st);
+        case kINT8: return launch_chan<kINT8>(a, st);
+    }
+    return hipErrorInvalidValue;
+}
 
 hipError_t launch_xgroups(int prec, const XArgs &a, hipStream_t st) {
     switch (prec) {

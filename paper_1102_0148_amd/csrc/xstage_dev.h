@@ -386,6 +386,128 @@ __device__ __forceinline__ void xg_loop(const uint4 *spec, int K, int a_pad, int
     wait_vm_lgkm0(0);  // the ring's last loads have landed
 }
 
+// ------------------------------------------------- whole-channel groups
+// Sixteen antenna blocks (4 x 4-block regions in 4 region rows): one
+// workgroup of eight waves per (channel, split) stages all 16 blocks of a
+// k-block in LDS once (slot s = block s; each wave loads two slots), so every
+// record of the channel is fetched once per split instead of twice as with
+// the three region groups.  Waves 2-7 take the six off-diagonal regions
+// (16 block pairs each); waves 0 and 1 take two diagonal regions each
+// (2 x 10 pairs), so with waves dealt to SIMDs in turn the SIMDs carry 36,
+// 36, 32 and 32 block pairs.  Two waves per SIMD keep 256 registers.
+constexpr int kXChanWaves = 8;
+
+__device__ __forceinline__ void xc_issue(const uint4 *spec, int K, int a_pad, int f, int kb, uint4 *stage, int wave) {
+    const int lane = threadIdx.x & 63;
+    const uint4 *rec = spec + ((int64_t)(kb >> 2) * K + f) * kTQB * a_pad + (kb & 3) * 4 * a_pad +
+                       (lane >> 4) * a_pad + (lane & 15);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int s = 2 * wave + i;
+        __builtin_amdgcn_global_load_lds(rec + s * 16, stage + s * 64, 16, 0, 0);
+    }
+}
+
+// The ring loop of xg_loop with every wave loading two slots; compute(stage)
+// runs the wave's regions on one k-block.
+template <typename C>
+__device__ __forceinline__ void xc_loop(const uint4 *spec, int K, int a_pad, int f, int kb0, int kb1, int wave,
+                                        uint4 *const (&st)[kXRing], C &&compute) {
+    constexpr int kPer = 2;
+    const int last = kb1 - 1;
+#pragma unroll
+    for (int s = 0; s + 1 < kXRing; ++s) xc_issue(spec, K, a_pad, f, min(kb0 + s, last), st[s], wave);
+    int kb = kb0;
+#pragma unroll 1
+    for (; kb + kXRing <= kb1; kb += kXRing) {
+#pragma unroll
+        for (int s = 0; s < kXRing; ++s) {
+            wait_vm_lgkm0((kXRing - 2) * kPer);
+            __builtin_amdgcn_s_barrier();
+            xc_issue(spec, K, a_pad, f, min(kb + s + kXRing - 1, last), st[(s + kXRing - 1) % kXRing], wave);
+            compute(st[s]);
+        }
+    }
+#pragma unroll
+    for (int s = 0; s + 1 < kXRing; ++s) {
+        if (kb + s < kb1) {
+            wait_vm_lgkm0((kXRing - 2 - s) * kPer);
+            __builtin_amdgcn_s_barrier();
+            compute(st[s]);
+        }
+    }
+    wait_vm_lgkm0(0);
+}
+
+// Writes one region's accumulators as partials (upper triangle, a <= b < N).
+template <int PREC>
+__device__ __forceinline__ void xc_store(const XArgs &a, int64_t obase, int I0, int J0, bool dreg,
+                                         typename AccT<PREC>::type (&accR)[4][4],
+                                         typename AccT<PREC>::type (&accI)[4][4]) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int I = 0; I < 4; ++I)
+#pragma unroll
+        for (int J = 0; J < 4; ++J) {
+            if (dreg && J < I) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int ia = (I0 + I) * 16 + 4 * (lane >> 4) + v;
+                const int ib = (J0 + J) * 16 + (lane & 15);
+                if (ia < a.N && ib < a.N && ia <= ib) {
+                    const int bl = ia * a.N - ia * (ia - 1) / 2 + (ib - ia);
+                    store_vis<PREC>(a.partial, obase + bl, accR[I][J], accI[I][J], v, ia == ib);
+                }
+            }
+        }
+}
+
+template <int PREC>
+__device__ __forceinline__ void x_chan(const XArgs &a, int unit, uint4 *const (&st)[kXRing]) {
+    typedef typename AccT<PREC>::type acc_t;
+    if (unit >= a.K * a.nsplit) return;  // the whole workgroup
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int f = unit % a.K, sp = unit / a.K;
+    const int kb0 = (int)((int64_t)sp * a.nkb / a.nsplit);
+    const int kb1 = (int)((int64_t)(sp + 1) * a.nkb / a.nsplit);
+    const int64_t obase = ((int64_t)sp * a.K + f) * a.nb;
+    const uint4 *spec = a.spec;
+    const int K = a.K, a_pad = a.a_pad;
+    if (wave < 2) {
+        // diagonal regions at blocks 4w and 4w + 8
+        const int rA = 4 * wave, rB = 4 * wave + 8;
+        acc_t aR[4][4], aI[4][4], bR[4][4], bI[4][4];
+#pragma unroll
+        for (int I = 0; I < 4; ++I)
+#pragma unroll
+            for (int J = 0; J < 4; ++J) aR[I][J] = aI[I][J] = bR[I][J] = bI[I][J] = acc_t{0, 0, 0, 0};
+        if (kb0 < kb1)
+            xc_loop(spec, K, a_pad, f, kb0, kb1, wave, st, [&](const uint4 *stg) {
+                xg_compute<PREC, true>(stg, rA, rA, aR, aI);
+                // one region's operands at a time: the two sets of
+                // accumulators leave room for no more
+                __builtin_amdgcn_sched_barrier(0);
+                xg_compute<PREC, true>(stg, rB, rB, bR, bI);
+            });
+        xc_store<PREC>(a, obase, rA, rA, true, aR, aI);
+        xc_store<PREC>(a, obase, rB, rB, true, bR, bI);
+    } else {
+        // off-diagonal regions (0,4) (0,8) (0,12) (4,8) (4,12) (8,12)
+        const int o = wave - 2;
+        const int I0 = o < 3 ? 0 : (o < 5 ? 4 : 8);
+        const int J0 = o < 3 ? 4 * (o + 1) : (o < 5 ? 4 * (o - 1) : 12);
+        acc_t aR[4][4], aI[4][4];
+#pragma unroll
+        for (int I = 0; I < 4; ++I)
+#pragma unroll
+            for (int J = 0; J < 4; ++J) aR[I][J] = aI[I][J] = acc_t{0, 0, 0, 0};
+        if (kb0 < kb1)
+            xc_loop(spec, K, a_pad, f, kb0, kb1, wave, st,
+                    [&](const uint4 *stg) { xg_compute<PREC, false>(stg, I0, J0, aR, aI); });
+        xc_store<PREC>(a, obase, I0, J0, false, aR, aI);
+    }
+}
+
 // A workgroup's share of the X-stage with LDS-staged groups: unit = group
 // (fastest), channel, split.  Wave w takes the group's region w.  int8 and
 // fp16 (P / Q form) only.
