@@ -115,29 +115,55 @@ hipError_t launch_group(const XArgs &a, hipStream_t st) {
 }
 
 // Whole-channel groups (16 antenna blocks): eight waves per workgroup, one
-// workgroup per (channel, split), the 16 blocks of a k-block staged once.
+// workgroup per (channel, split), the 16 blocks of a k-block staged once, in
+// a ring of kXChanRing stages (one workgroup per CU would leave LDS for up to
+// eight; depths 3, 4, 6 and 8 measured the same at N = 256).
+#ifndef X_CHAN_RING
+#define X_CHAN_RING 3
+#endif
+constexpr int kXChanRing = X_CHAN_RING;
+
 template <int PREC>
 __global__ __launch_bounds__(kXChanWaves * 64, 1) void xchan_kernel(XArgs a) {
+    // one array per stage, as in xgroup_kernel
     __shared__ __attribute__((aligned(16))) uint4 st0[kXStage];
     __shared__ __attribute__((aligned(16))) uint4 st1[kXStage];
     __shared__ __attribute__((aligned(16))) uint4 st2[kXStage];
-#if X_RING >= 4
+#if X_CHAN_RING >= 4
     __shared__ __attribute__((aligned(16))) uint4 st3[kXStage];
 #endif
-#if X_RING >= 5
+#if X_CHAN_RING >= 5
     __shared__ __attribute__((aligned(16))) uint4 st4[kXStage];
 #endif
-    uint4 *const st[kXRing] = {st0, st1, st2
-#if X_RING >= 4
-                               , st3
+#if X_CHAN_RING >= 6
+    __shared__ __attribute__((aligned(16))) uint4 st5[kXStage];
 #endif
-#if X_RING >= 5
-                               , st4
+#if X_CHAN_RING >= 7
+    __shared__ __attribute__((aligned(16))) uint4 st6[kXStage];
+#endif
+#if X_CHAN_RING >= 8
+    __shared__ __attribute__((aligned(16))) uint4 st7[kXStage];
+#endif
+    uint4 *const st[kXChanRing] = {st0, st1, st2
+#if X_CHAN_RING >= 4
+                                   , st3
+#endif
+#if X_CHAN_RING >= 5
+                                   , st4
+#endif
+#if X_CHAN_RING >= 6
+                                   , st5
+#endif
+#if X_CHAN_RING >= 7
+                                   , st6
+#endif
+#if X_CHAN_RING >= 8
+                                   , st7
 #endif
     };
     // logical workgroup as in xstage_kernel: neighbouring channels share an XCD
     const int lb = (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
-    x_chan<PREC>(a, lb, st);
+    x_chan<PREC, kXChanRing>(a, lb, st);
 }
 
 template <int PREC>

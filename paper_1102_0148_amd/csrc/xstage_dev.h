@@ -408,30 +408,30 @@ __device__ __forceinline__ void xc_issue(const uint4 *spec, int K, int a_pad, in
     }
 }
 
-// The ring loop of xg_loop with every wave loading two slots; compute(stage)
-// runs the wave's regions on one k-block.
-template <typename C>
+// The ring loop of xg_loop over R stages with every wave loading two slots;
+// compute(stage) runs the wave's regions on one k-block.
+template <int R, typename C>
 __device__ __forceinline__ void xc_loop(const uint4 *spec, int K, int a_pad, int f, int kb0, int kb1, int wave,
-                                        uint4 *const (&st)[kXRing], C &&compute) {
+                                        uint4 *const (&st)[R], C &&compute) {
     constexpr int kPer = 2;
     const int last = kb1 - 1;
 #pragma unroll
-    for (int s = 0; s + 1 < kXRing; ++s) xc_issue(spec, K, a_pad, f, min(kb0 + s, last), st[s], wave);
+    for (int s = 0; s + 1 < R; ++s) xc_issue(spec, K, a_pad, f, min(kb0 + s, last), st[s], wave);
     int kb = kb0;
 #pragma unroll 1
-    for (; kb + kXRing <= kb1; kb += kXRing) {
+    for (; kb + R <= kb1; kb += R) {
 #pragma unroll
-        for (int s = 0; s < kXRing; ++s) {
-            wait_vm_lgkm0((kXRing - 2) * kPer);
+        for (int s = 0; s < R; ++s) {
+            wait_vm_lgkm0((R - 2) * kPer);
             __builtin_amdgcn_s_barrier();
-            xc_issue(spec, K, a_pad, f, min(kb + s + kXRing - 1, last), st[(s + kXRing - 1) % kXRing], wave);
+            xc_issue(spec, K, a_pad, f, min(kb + s + R - 1, last), st[(s + R - 1) % R], wave);
             compute(st[s]);
         }
     }
 #pragma unroll
-    for (int s = 0; s + 1 < kXRing; ++s) {
+    for (int s = 0; s + 1 < R; ++s) {
         if (kb + s < kb1) {
-            wait_vm_lgkm0((kXRing - 2 - s) * kPer);
+            wait_vm_lgkm0((R - 2 - s) * kPer);
             __builtin_amdgcn_s_barrier();
             compute(st[s]);
         }
@@ -462,8 +462,8 @@ __device__ __forceinline__ void xc_store(const XArgs &a, int64_t obase, int I0, 
         }
 }
 
-template <int PREC>
-__device__ __forceinline__ void x_chan(const XArgs &a, int unit, uint4 *const (&st)[kXRing]) {
+template <int PREC, int R>
+__device__ __forceinline__ void x_chan(const XArgs &a, int unit, uint4 *const (&st)[R]) {
     typedef typename AccT<PREC>::type acc_t;
     if (unit >= a.K * a.nsplit) return;  // the whole workgroup
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);

@@ -28,7 +28,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "tuned_tiles.json")
 ARCH = "gfx950"
 LDS_LIMIT = 160 * 1024
-SPLITS = (4, 8, 12, 16, 24, 32, 48, 64)
+SPLITS = (1, 2, 4, 8, 12, 16, 24, 32, 48, 64)
 # spectra one partial may sum, per form: fp32 partials stay short for
 # accuracy (its three-product form cancels), fp16's error is its spectra's up
 # to 16384; int16 digit sums must stay exact in int32; int8 sums always are
