@@ -8,10 +8,23 @@ namespace {
 
 // acc[e] += partial[0][e] + partial[1][e] + ... in this order, in float64
 // (Section 1: the cross power spectra are accumulated to the cadence).
+// Runs of 16 partials are loaded before any is added, so their loads are in
+// flight together (as one loop each load waited for the previous add).
 template <typename P>
 __device__ __forceinline__ void dump_one(const P *partial, double2 *acc, int nsplit, int64_t n, int64_t e) {
     double2 v = acc[e];
-    for (int s = 0; s < nsplit; ++s) {
+    int s = 0;
+    for (; s + 16 <= nsplit; s += 16) {
+        P p[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) p[j] = partial[(int64_t)(s + j) * n + e];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            v.x += (double)p[j].x;
+            v.y += (double)p[j].y;
+        }
+    }
+    for (; s < nsplit; ++s) {
         const P p = partial[(int64_t)s * n + e];
         v.x += (double)p.x;
         v.y += (double)p.y;
