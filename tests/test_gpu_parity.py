@@ -74,6 +74,31 @@ def test_fstage_fp32_spectra_match_oracle(K):
     np.testing.assert_array_equal(got[:, :, K // 2], ref[:, :, K // 2].round())
 
 
+@pytest.mark.parametrize("K", [256, 512])
+def test_matrix_core_transform_spectra(K):
+    """The transform of the reduced-precision records (on the matrix cores at
+    K = 256 and 512) through fp16 records: every value within one f16 step of
+    the float64 oracle's spectrum, almost all equal to its f16 rounding, and
+    bins 0 and K/2 (integers, here below 2048) bit for bit."""
+    N, S = 5, 12
+    print(f"\n[matrix-core transform] N={N} K={K} S={S}", flush=True)
+    r = synth.recipe_plain(N=N, two_k=2 * K, seed=41)
+    packed = _packed(r, S)
+    c = corr.Correlator(N, K, S, precision="fp16")
+    c.process(packed)
+    buf, n = c.debug_read_spectra()
+    assert n == S
+    got = corr.records_to_spectra(buf, corr.CORR_FP16, N, K, S)
+    ref = oracle.spectra(packed.cpu().numpy(), S, N, K)
+    for g, x in ((got.real, ref.real), (got.imag, ref.imag)):
+        step = 2.0 ** (np.floor(np.log2(np.maximum(np.abs(x), 2.0 ** -14))) - 10)
+        assert np.all(np.abs(g - x) <= step), np.max(np.abs(g - x) / step)
+        assert np.mean(g != x.astype(np.float16).astype(np.float64)) <= 1e-3
+    for b in (0, K // 2):
+        assert np.max(np.abs(ref[:, :, b])) < 2048
+        np.testing.assert_array_equal(got[:, :, b], ref[:, :, b].round())
+
+
 def test_fstage_extreme_samples():
     """All -8 and all 7 samples (largest magnitudes): DC = 2K x, other bins 0."""
     N, K, S = 3, 256, 4
