@@ -77,9 +77,10 @@ def test_fstage_fp32_spectra_match_oracle(K):
 @pytest.mark.parametrize("K", [256, 512])
 def test_matrix_core_transform_spectra(K):
     """The transform of the reduced-precision records (on the matrix cores at
-    K = 256 and 512) through fp16 records: every value within one f16 step of
-    the float64 oracle's spectrum, almost all equal to its f16 rounding, and
-    bins 0 and K/2 (integers, here below 2048) bit for bit."""
+    K = 256 and 512) through fp16 records: every value within half an f16
+    step (the record's rounding) plus the fp32 transform's error budget of
+    the float64 oracle's spectrum, and bins 0 and K/2 (integers, here below
+    2048) bit for bit."""
     N, S = 5, 12
     print(f"\n[matrix-core transform] N={N} K={K} S={S}", flush=True)
     r = synth.recipe_plain(N=N, two_k=2 * K, seed=41)
@@ -90,10 +91,11 @@ def test_matrix_core_transform_spectra(K):
     assert n == S
     got = corr.records_to_spectra(buf, corr.CORR_FP16, N, K, S)
     ref = oracle.spectra(packed.cpu().numpy(), S, N, K)
+    budget = 2e-6 * np.sqrt(np.mean(np.abs(ref) ** 2)) * math.log2(2 * K)
     for g, x in ((got.real, ref.real), (got.imag, ref.imag)):
         step = 2.0 ** (np.floor(np.log2(np.maximum(np.abs(x), 2.0 ** -14))) - 10)
-        assert np.all(np.abs(g - x) <= step), np.max(np.abs(g - x) / step)
-        assert np.mean(g != x.astype(np.float16).astype(np.float64)) <= 1e-3
+        excess = np.abs(g - x) - 0.5 * step
+        assert np.all(excess <= budget), np.max(excess) / budget
     for b in (0, K // 2):
         assert np.max(np.abs(ref[:, :, b])) < 2048
         np.testing.assert_array_equal(got[:, :, b], ref[:, :, b].round())
