@@ -274,19 +274,23 @@ __device__ __forceinline__ void dft256_mfma(uint32_t p, const MfmaFft<M> &k, f4_
     f4_t yr = mfma_h(a, k.dl[0], zero), yi = mfma_h(a, k.dl[1], zero);
     yr = mfma_h(a, k.dh[0], yr);
     yi = mfma_h(a, k.dh[1], yi);
+    // The multiplier -1 of lo = hi * (-1) + y, kept opaque: a known -1 turns
+    // the product into a subtraction, which has no mixed-precision form.
+    float m1 = -1.0f;
+    asm volatile("" : "+v"(m1));
     h8_t bh, bl;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const float2 y = cmul(make_float2(yr[i], yi[i]), k.w[i]);
-        // hi: y cut to 11 significant bits (exact in f16 down to 2^-14;
-        // below that its conversion rounds by at most 2^-25), lo = y - hi
-        // (exact in f32) rounded to f16
-        const float hr = __uint_as_float(__float_as_uint(y.x) & 0xffffe000u);
-        const float hm = __uint_as_float(__float_as_uint(y.y) & 0xffffe000u);
-        bh[2 * i] = (_Float16)hr;
-        bh[2 * i + 1] = (_Float16)hm;
-        bl[2 * i] = (_Float16)(y.x - hr);
-        bl[2 * i + 1] = (_Float16)(y.y - hm);
+        // hi: y rounded toward zero to f16, i.e. cut to 11 significant bits
+        // (below 2^-14 the cut is coarser, by at most 2^-24), lo = y - hi,
+        // exact in the f32 arithmetic of the mixed-precision fma, rounded to
+        // f16
+        const h2_t h = __builtin_bit_cast(h2_t, __builtin_amdgcn_cvt_pkrtz(y.x, y.y));
+        bh[2 * i] = h[0];
+        bh[2 * i + 1] = h[1];
+        bl[2 * i] = (_Float16)__builtin_fmaf((float)h[0], m1, y.x);
+        bl[2 * i + 1] = (_Float16)__builtin_fmaf((float)h[1], m1, y.y);
     }
     zr = mfma_h(k.dl[0], bh, zero);
     zi = mfma_h(k.dl[1], bh, zero);
@@ -347,17 +351,33 @@ __device__ __forceinline__ float nib(uint32_t w, int off) {
     return (float)((int)(w << (28 - off)) >> 28);
 }
 
-// Adds to wsat (wave-uniform) the number of the wavefront's values v with
-// |v| >= lim.  The exact count runs only when some lane's largest |v| reaches
-// lim, which saturation makes rare: otherwise a running maximum is all.
+// qm[t] = 1.5 * 2^23 + q[t] with q = clamp(rint(x[t] sc), -lim, lim).  One
+// fused x sc + 1.5 * 2^23 rounds the exact product to the nearest integer
+// (ties to even) and leaves it in the low bits of the sum (|x sc| < 2^22; a
+// larger product lands beyond the clamp bounds, which the clamp then takes).
+// The values share one scale sc > 0, so one can round past lim only if
+// sc max|x| >= lim + 0.5, and the rounded product keeps that bound (never
+// misses such a value).  The clamp, and the exact count of the values whose
+// rounded magnitude exceeds lim (added to wsat, wave-uniform), run only in a
+// wavefront where some lane reaches the bound, which saturation makes rare.
 template <int NV>
-__device__ __forceinline__ void count_saturated(const float (&v)[NV], float lim, unsigned &wsat) {
+__device__ __forceinline__ void quantise(const float (&x)[NV], float sc, float lim, unsigned &wsat,
+                                         float (&qm)[NV]) {
+    constexpr float kMagic = 12582912.0f;
+    // max|x| as a chain of three-operand maxima (the NaN-propagating form
+    // needs no canonicalised operands; the values here are finite)
     float m = 0.0f;
 #pragma unroll
-    for (int t = 0; t < NV; t += 2) m = fmaxf(m, fmaxf(fabsf(v[t]), fabsf(v[t + 1])));
-    if (__ballot(m >= lim)) {
+    for (int t = 0; t < NV; t += 2)
+        m = __builtin_elementwise_maximum(__builtin_elementwise_maximum(m, fabsf(x[t])), fabsf(x[t + 1]));
 #pragma unroll
-        for (int t = 0; t < NV; ++t) wsat += (unsigned)__popcll(__ballot(fabsf(v[t]) >= lim));
+    for (int t = 0; t < NV; ++t) qm[t] = __builtin_fmaf(x[t], sc, kMagic);
+    if (__ballot(m * sc >= lim + 0.5f)) {
+#pragma unroll
+        for (int t = 0; t < NV; ++t) {
+            wsat += (unsigned)__popcll(__ballot(fabsf(qm[t] - kMagic) > lim));
+            qm[t] = __builtin_amdgcn_fmed3f(qm[t], kMagic - lim, kMagic + lim);
+        }
     }
 }
 
@@ -365,8 +385,8 @@ __device__ __forceinline__ void count_saturated(const float (&v)[NV], float lim,
 // [re x TS][im x TS] of the precision's type.  int8: the record holds
 // q = clamp(rint(x sc), -127, 127), rounding to nearest even, with re[] and
 // im[] here already multiplied by two and sc halved (both exact, so x sc is
-// the same float); wsat (wave-uniform) counts the values with |x sc| >= 127.5,
-// those whose rounded magnitude exceeds 127.
+// the same product); wsat (wave-uniform) counts the values whose rounded
+// magnitude exceeds 127 (int16: 32512).
 template <int PREC, int TS>
 __device__ __forceinline__ uint4 make_record(const float *re, const float *im, float sc, unsigned &wsat) {
     uint4 out;
@@ -399,16 +419,15 @@ __device__ __forceinline__ uint4 make_record(const float *re, const float *im, f
         // Record: [h of re x4][h of im x4][l of re x4][l of im x4].
         constexpr float kMagic = 12582912.0f;
         uint32_t hb[8], lb[8];
-        float v[8];
+        float x[8], qm[8];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) v[t] = (t < 4 ? re[t] : im[t - 4]) * sc;
-        count_saturated<8>(v, (float)kI16Max + 0.5f, wsat);
+        for (int t = 0; t < 8; ++t) x[t] = t < 4 ? re[t] : im[t - 4];
+        quantise<8>(x, sc, (float)kI16Max, wsat, qm);
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
-            const float qm = __builtin_amdgcn_fmed3f(v[t], -(float)kI16Max, (float)kI16Max) + kMagic;
-            const float hm = fmaf(qm - kMagic, 1.0f / 255.0f, kMagic);
+            const float hm = fmaf(qm[t] - kMagic, 1.0f / 255.0f, kMagic);
             hb[t] = __float_as_uint(hm);
-            lb[t] = __float_as_uint(qm) + __float_as_uint(hm);
+            lb[t] = __float_as_uint(qm[t]) + __float_as_uint(hm);
         }
         uint32_t w[4];
 #pragma unroll
@@ -421,20 +440,17 @@ __device__ __forceinline__ uint4 make_record(const float *re, const float *im, f
         out = make_uint4(w[0], w[1], w[2], w[3]);
     } else {
         static_assert(TS == 8, "int8 record");
-        // rint and the clamp to +-127 commute, so clamp first; adding 1.5 * 2^23
-        // then rounds to the nearest integer (ties to even) and leaves it, as
-        // two's complement, in the low byte of the sum
-        float v[16];
+        // the low byte of 1.5 * 2^23 + q is q as two's complement
+        float x[16], qm[16];
 #pragma unroll
-        for (int t = 0; t < 16; ++t) v[t] = (t < 8 ? re[t] : im[t - 8]) * sc;
-        count_saturated<16>(v, 127.5f, wsat);
+        for (int t = 0; t < 16; ++t) x[t] = t < 8 ? re[t] : im[t - 8];
+        quantise<16>(x, sc, 127.0f, wsat, qm);
         uint32_t w[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             uint32_t b[4];
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
-                b[t] = __float_as_uint(__builtin_amdgcn_fmed3f(v[4 * k + t], -127.0f, 127.0f) + 12582912.0f);
+            for (int t = 0; t < 4; ++t) b[t] = __float_as_uint(qm[4 * k + t]);
             // low bytes of b[0..3] -> bytes 0..3 of the word
             w[k] = __builtin_amdgcn_perm(b[1], b[0], 0x0c0c0400u) | __builtin_amdgcn_perm(b[3], b[2], 0x04000c0cu);
         }
