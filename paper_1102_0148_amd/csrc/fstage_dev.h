@@ -186,8 +186,9 @@ struct PassTw {
 // both 16-point DFTs are real 16 x 32 by 32 x 16 products, one transform per
 // wavefront at a time, on v_mfma_f32_16x16x32_f16: lane (j = lane mod 16,
 // g = lane / 16) holds row j of the left operand and column j of the right
-// one over contraction positions 8g .. 8g + 7, i.e. (point 4g + i, re / im)
-// for i < 4, and gets rows 4g + i of column j of the result.  The real form of
+// one over contraction positions 8g .. 8g + 7, i.e. the real parts of points
+// 4g .. 4g + 3, then their imaginary parts, and gets rows 4g + i of column j
+// of the result.  The real form of
 // W16 in that layout is the same register set in both products: the right
 // operand of the first (contraction s, column c = j) and the left operand of
 // the second (row d = j, contraction f).  Each DFT is summed from f16 halves,
@@ -219,8 +220,13 @@ struct MfmaFft {
     float2 w[4];        // W256^(f c), f = 4g + i, c = j
     float2 w2[P == 2 ? 4 : 1];  // W512^q, q = j + 16 (4g + i)
     uint32_t sel01[P], sel23[P];
+    // -1, opaque to the optimizer: a known -1 turns the product of the
+    // split's fma into a subtraction, which has no mixed-precision form
+    float m1;
     __device__ __forceinline__ void load(int, const float2 *twM) {
         const int lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
+        m1 = -1.0f;
+        asm volatile("" : "+v"(m1));
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int s = 4 * g + i;
@@ -233,8 +239,8 @@ struct MfmaFft {
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
                     const _Float16 h = (_Float16)v[b][c];
-                    dh[b][2 * i + c] = h;
-                    dl[b][2 * i + c] = (_Float16)(v[b][c] - (float)h);
+                    dh[b][4 * c + i] = h;
+                    dl[b][4 * c + i] = (_Float16)(v[b][c] - (float)h);
                 }
             w[i] = twM[((s * j) & 255) * (M / 256)];
             if constexpr (P == 2) w2[i] = twM[j + 16 * s];
@@ -258,39 +264,45 @@ __device__ __forceinline__ f4_t mfma_h(h8_t a, h8_t b, f4_t c) {
 // of p, to the lane's four outputs Z[j + 16 (4g + i)] (zr, zi).
 template <int M>
 __device__ __forceinline__ void dft256_mfma(uint32_t p, const MfmaFft<M> &k, f4_t &zr, f4_t &zi) {
-    // offset nibbles u = n + 8 as 1024 + u in f16, then minus 1032: exact
+    // offset nibbles u = n + 8 as 1024 + u in f16 (byte u under the exponent
+    // byte 0x64), then minus 1032: exact.  Real parts are the low nibbles.
     const uint32_t t = p ^ 0x88888888u;
     const uint32_t lo = t & 0x0f0f0f0fu, hi = (t >> 4) & 0x0f0f0f0fu;
+    const uint32_t bits[4] = {__builtin_amdgcn_perm(0x64646464u, lo, 0x04010400u),
+                              __builtin_amdgcn_perm(0x64646464u, lo, 0x04030402u),
+                              __builtin_amdgcn_perm(0x64646464u, hi, 0x04010400u),
+                              __builtin_amdgcn_perm(0x64646464u, hi, 0x04030402u)};
     h8_t a;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const uint32_t bits =
-            __builtin_amdgcn_perm(hi, lo, (uint32_t)i | 0x0c00u | (uint32_t)(i + 4) << 16 | 0x0c000000u) | 0x64006400u;
-        const h2_t v = __builtin_bit_cast(h2_t, bits) - h2_t{(_Float16)1032.0f, (_Float16)1032.0f};
-        a[2 * i] = v[0];
-        a[2 * i + 1] = v[1];
+    for (int w = 0; w < 4; ++w) {
+        const h2_t v = __builtin_bit_cast(h2_t, bits[w]) - h2_t{(_Float16)1032.0f, (_Float16)1032.0f};
+        a[2 * w] = v[0];
+        a[2 * w + 1] = v[1];
     }
     const f4_t zero = {0.0f, 0.0f, 0.0f, 0.0f};
     f4_t yr = mfma_h(a, k.dl[0], zero), yi = mfma_h(a, k.dl[1], zero);
     yr = mfma_h(a, k.dh[0], yr);
     yi = mfma_h(a, k.dh[1], yi);
-    // The multiplier -1 of lo = hi * (-1) + y, kept opaque: a known -1 turns
-    // the product into a subtraction, which has no mixed-precision form.
-    float m1 = -1.0f;
-    asm volatile("" : "+v"(m1));
+    float2 y[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) y[i] = cmul(make_float2(yr[i], yi[i]), k.w[i]);
+    // hi: y rounded toward zero to f16, i.e. cut to 11 significant bits
+    // (below 2^-14 the cut is coarser, by at most 2^-24), lo = y - hi, exact
+    // in the f32 arithmetic of the mixed-precision fma, rounded to f16; real
+    // parts at positions 0-3, imaginary parts at 4-7
     h8_t bh, bl;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const float2 y = cmul(make_float2(yr[i], yi[i]), k.w[i]);
-        // hi: y rounded toward zero to f16, i.e. cut to 11 significant bits
-        // (below 2^-14 the cut is coarser, by at most 2^-24), lo = y - hi,
-        // exact in the f32 arithmetic of the mixed-precision fma, rounded to
-        // f16
-        const h2_t h = __builtin_bit_cast(h2_t, __builtin_amdgcn_cvt_pkrtz(y.x, y.y));
-        bh[2 * i] = h[0];
-        bh[2 * i + 1] = h[1];
-        bl[2 * i] = (_Float16)__builtin_fmaf((float)h[0], m1, y.x);
-        bl[2 * i + 1] = (_Float16)__builtin_fmaf((float)h[1], m1, y.y);
+    for (int i = 0; i < 4; i += 2) {
+        const h2_t hr = __builtin_bit_cast(h2_t, __builtin_amdgcn_cvt_pkrtz(y[i].x, y[i + 1].x));
+        const h2_t hm = __builtin_bit_cast(h2_t, __builtin_amdgcn_cvt_pkrtz(y[i].y, y[i + 1].y));
+        bh[i] = hr[0];
+        bh[i + 1] = hr[1];
+        bh[4 + i] = hm[0];
+        bh[4 + i + 1] = hm[1];
+        bl[i] = (_Float16)__builtin_fmaf((float)hr[0], k.m1, y[i].x);
+        bl[i + 1] = (_Float16)__builtin_fmaf((float)hr[1], k.m1, y[i + 1].x);
+        bl[4 + i] = (_Float16)__builtin_fmaf((float)hm[0], k.m1, y[i].y);
+        bl[4 + i + 1] = (_Float16)__builtin_fmaf((float)hm[1], k.m1, y[i + 1].y);
     }
     zr = mfma_h(k.dl[0], bh, zero);
     zi = mfma_h(k.dl[1], bh, zero);
