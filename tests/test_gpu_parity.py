@@ -304,6 +304,32 @@ def test_fstage_bit_identical_across_groups(prec, groups):
             np.testing.assert_array_equal(sp, ref)
 
 
+@pytest.mark.parametrize("prec,lim", [("int8", 127), ("int16", 32512)])
+def test_saturation_count_matches_oracle_spectra(prec, lim):
+    """The saturation counter counts the components whose rounded code lies
+    beyond the clamp (Section 4's conversion to short integers).  The
+    calibration window is three times quieter than the rest, so the later
+    spectra clip often (int8 at 4 rms of the window: about one component in
+    six; int16 at 8: about one in two hundred).  Expected: the components of
+    the oracle's spectra, times the GPU's scales, that round beyond the
+    clamp; only components within rounding of the bound may differ."""
+    N, K, S, W = 12, 256, 1536, corr.CORR_CALIB_SPECTRA
+    x = synth.samples(synth.recipe_plain(N=N, two_k=2 * K, seed=21), 0, S)
+    x[:W] = torch.round(x[:W].float() / 3).to(torch.int8)
+    packed = synth.pack(x).contiguous()
+    print(f"\n[saturation] {prec} N={N} K={K} S={S}", flush=True)
+    c = corr.Correlator(N, K, S, precision=prec)
+    c.process(packed.cuda())
+    got = c.stats()["int8_saturated"]
+    scales = c.read_scales()
+    spec = oracle.spectra(packed.numpy(), S, N, K)
+    v = np.stack([spec.real, spec.imag], -1) * scales[None, :, :, None].astype(np.float64)
+    want = int(np.count_nonzero(np.abs(np.rint(v)) > lim))
+    assert want > (S - W) * N * K * 2 // (10 if prec == "int8" else 1000)
+    assert abs(got - want) <= 2 + want // 10000, (got, want)
+    c.close()
+
+
 def test_int8_physical_units_match_fp64():
     """De-scaled int8 visibilities estimate the float64 ones: the coefficient
     error is set by the quantisation step (1/127 of 4 rms per component)."""
