@@ -367,6 +367,23 @@ def batch(corr, torch, metrics, steps, warmup):
     return out
 
 
+def batch_fresh_process(steps, warmup):
+    """The batch leg in a child process of its own.  A cooperative launch (the
+    fused pipeline's kernel, which the headline step runs for fp16) slows every
+    later multi-branch graph replay in the same process by about a tenth
+    (int8 batch 2.07 -> 2.28 ms, the separate launches unchanged), so the
+    batch and the separate launches it is compared with are both timed in a
+    process that has made none.  The child's progress lines go to stderr."""
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--only-batch", "--steps", str(steps), "--warmup", str(warmup)]
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, timeout=900)
+    if r.returncode != 0:
+        raise RuntimeError(f"batch leg failed with exit status {r.returncode}")
+    out = json.loads(r.stdout.strip().splitlines()[-1])
+    out["process"] = "fresh: no cooperative launch before it"
+    return out
+
+
 def x_mfma(metrics, N, K, S, prec, x_ms):
     """The X-stage's issued MFMA rate against the dense peak of its form
     (issued operations from the block-pair count; rocprofv3's
@@ -459,6 +476,9 @@ def main():
                     help="extra workloads to run after the headline step (comma list)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (scale reference for HBM counters)")
+    ap.add_argument("--only-batch", action="store_true",
+                    help="run the batch leg alone (--steps / --warmup as given) and print its JSON "
+                         "(the full run starts it this way, in a process of its own)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -470,6 +490,9 @@ def main():
     from paper_1102_0148_amd import metrics
 
     torch.cuda.set_device(0)
+    if args.only_batch:
+        print(json.dumps(batch(corr, torch, metrics, args.steps, args.warmup)))
+        return
     if args.copy_probe:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -596,7 +619,7 @@ def main():
     if "large_n" in legs:
         out["large_n"] = large_n(corr, torch, metrics, max(2, args.steps // 3), 1)
     if "batch" in legs:
-        out["batch"] = batch(corr, torch, metrics, max(3, args.steps // 3), 1)
+        out["batch"] = batch_fresh_process(max(3, args.steps // 3), 1)
     if not args.no_cpu_baseline:
         import numpy as np
         import synth
