@@ -318,15 +318,25 @@ def test_saturation_count_matches_oracle_spectra(prec, lim):
     x[:W] = torch.round(x[:W].float() / 3).to(torch.int8)
     packed = synth.pack(x).contiguous()
     print(f"\n[saturation] {prec} N={N} K={K} S={S}", flush=True)
-    c = corr.Correlator(N, K, S, precision=prec)
+    c = corr.Correlator(N, K, S, precision=prec, tiles=dict(chunk_spectra=S))
     c.process(packed.cuda())
     got = c.stats()["int8_saturated"]
     scales = c.read_scales()
+    buf, n = c.debug_read_spectra()
+    assert n == S
     spec = oracle.spectra(packed.numpy(), S, N, K)
     v = np.stack([spec.real, spec.imag], -1) * scales[None, :, :, None].astype(np.float64)
     want = int(np.count_nonzero(np.abs(np.rint(v)) > lim))
     assert want > (S - W) * N * K * 2 // (10 if prec == "int8" else 1000)
     assert abs(got - want) <= 2 + want // 10000, (got, want)
+    # the codes themselves, clamped ones included, follow the oracle's rule
+    mode = corr.CORR_INT8 if prec == "int8" else corr.CORR_INT16
+    q_gpu = corr.records_to_spectra(buf, mode, N, K, S).astype(np.int32)
+    q_ref = (oracle.quantise if prec == "int8" else oracle.quantise16)(spec, scales).astype(np.int32)
+    assert np.max(np.abs(q_gpu)) == lim
+    diff = q_gpu - q_ref
+    assert np.max(np.abs(diff)) <= 1
+    assert np.mean(diff != 0) <= 1e-3
     c.close()
 
 
