@@ -86,7 +86,9 @@ def lookup(N: int, K: int, S: int, prec: str, batch=False, path: str = TABLE, mo
 
 def _time_single(corr, torch, N, K, S, prec, tiles, x, reps=3, warm=1) -> Dict[str, float]:
     """Per-integration stage times (ms) of one tile choice: F-stage, X-stage
-    plus dump, calibration and their total."""
+    plus dump, calibration and their total, and the end-to-end time of an
+    integration (process and an asynchronous read between HIP events, so the
+    gaps between launches count too)."""
     c = corr.Correlator(N, K, S, precision=prec, tiles=tiles)
     dst = torch.empty(c.nb * K * 2, dtype=torch.float64, device="cuda")
     try:
@@ -94,12 +96,18 @@ def _time_single(corr, torch, N, K, S, prec, tiles, x, reps=3, warm=1) -> Dict[s
             c.process(x)
             c.read_cps_async(dst)
         c.enable_timing(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
         for _ in range(reps):
             c.process(x)
             c.read_cps_async(dst)
+        e1.record()
+        torch.cuda.synchronize()
         st = c.stats()
         t = {"f": st["ms_f"] / reps, "x": (st["ms_x"] + st["ms_dump"]) / reps, "calib": st["ms_calib"] / reps}
         t["total"] = t["f"] + t["x"] + t["calib"]
+        t["e2e"] = e0.elapsed_time(e1) / reps
         return t
     finally:
         c.close()
@@ -124,12 +132,28 @@ def _rounds(corr, torch, N, K, S, prec, x, cands, stage, rounds=3, reps=4, log=p
     return [(json.loads(k), _median(v)) for k, v in seen.items()]
 
 
-def tune_single(N: int, K: int, S: int, prec: str, log=print) -> Tuple[dict, float, List[Tuple[dict, float]]]:
+def final_candidates(top: List[dict], group: int, incumbent: Optional[dict] = None) -> List[dict]:
+    """The choices of tune_single's last stage: the best (chunk, splits) pairs
+    with the chosen F group, and the table's present entry (its three tiles)
+    where there is one, so that a re-tune keeps it unless another choice
+    beats it side by side on the same GPU."""
+    out = [dict(t, f_group=group) for t in top]
+    if incumbent and all(k in incumbent for k in ("chunk_spectra", "x_splits", "f_group")):
+        inc = {k: incumbent[k] for k in ("chunk_spectra", "x_splits", "f_group")}
+        if inc not in out:
+            out.append(inc)
+    return out
+
+
+def tune_single(N: int, K: int, S: int, prec: str, log=print,
+                incumbent: Optional[dict] = None) -> Tuple[dict, float, List[Tuple[dict, float]]]:
     """Stage 1 times every (chunk, splits) at the default F group; stage 2
     picks the group by the F-stage time alone (the only stage it changes),
     timing the groups in turn at the best chunk; stage 3 times the four best
-    (chunk, splits) pairs of stage 1 with that group in turn and keeps the
-    lowest median total (ties as in `pick`)."""
+    (chunk, splits) pairs of stage 1 with that group, and the incumbent
+    table entry, in turn and keeps the lowest median end-to-end time (ties
+    as in `pick`): the stage timers leave out the gaps between launches,
+    which a choice with more chunks pays for."""
     import torch
     import paper_1102_0148_amd as corr
     import synth
@@ -149,7 +173,10 @@ def tune_single(N: int, K: int, S: int, prec: str, log=print) -> Tuple[dict, flo
     by_f = _rounds(corr, torch, N, K, S, prec, x,
                    [{"chunk_spectra": chunk, "x_splits": splits, "f_group": g} for g in groups], "f", log=log)
     group = min(by_f, key=lambda r: r[1])[0]["f_group"]
-    final = _rounds(corr, torch, N, K, S, prec, x, [dict(t, f_group=group) for t in top], "total", log=log)
+    # integrations are cheap next to building a correlator: ten per timing,
+    # five rounds, against the drift of the clock between rounds
+    final = _rounds(corr, torch, N, K, S, prec, x, final_candidates(top, group, incumbent), "e2e",
+                    rounds=5, reps=10, log=log)
     best, best_ms = pick(final)
     return best, best_ms, results + final
 
@@ -292,7 +319,7 @@ def main(argv: Optional[Iterable[str]] = None):
             best = {k: old[k] for k in ("chunk_spectra", "x_splits", "f_group")}
             ms = old.get("ms", 0.0)
         else:
-            best, ms, _ = tune_single(N, K, S, prec)
+            best, ms, _ = tune_single(N, K, S, prec, incumbent=old)
         entry = dict(best, ms=round(ms, 4), pipeline="staged")
         fbest, fms, sms = tune_pipeline(N, K, S, prec, best)
         if fbest is not None:

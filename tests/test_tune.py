@@ -58,3 +58,18 @@ def test_fused_candidates_one_layout_each():
     assert tune.fused_candidates(44, 256, 1000, "int8")[0]["chunk_spectra"] <= 1024
     assert tune.fused_candidates(44, 256, 65536, "int16") == []
     assert tune.fused_candidates(64, 256, 65536, "fp32") == []
+
+
+def test_final_candidates_keep_the_incumbent():
+    """The last stage times the best pairs with the chosen F group and the
+    table's present entry, once, whatever else the entry holds."""
+    top = [{"chunk_spectra": 65536, "x_splits": 4, "f_group": 8}, {"chunk_spectra": 32768, "x_splits": 8, "f_group": 8}]
+    inc = {"chunk_spectra": 65536, "x_splits": 4, "f_group": 2, "ms": 1.3, "pipeline": "staged"}
+    out = tune.final_candidates(top, 2, inc)
+    assert out == [{"chunk_spectra": 65536, "x_splits": 4, "f_group": 2},
+                   {"chunk_spectra": 32768, "x_splits": 8, "f_group": 2}]
+    inc2 = dict(inc, x_splits=16)
+    assert tune.final_candidates(top, 2, inc2)[-1] == {"chunk_spectra": 65536, "x_splits": 16, "f_group": 2}
+    assert len(tune.final_candidates(top, 2, None)) == 2
+    # a batch or fused entry (no tile triple) is not a staged candidate
+    assert len(tune.final_candidates(top, 2, {"x_splits": 4, "ms": 1.0})) == 2
