@@ -223,7 +223,8 @@ def _time_e2e(corr, torch, N, K, S, prec, x, tiles=None, pipeline=None, reps=4, 
 
 def tune_pipeline(N: int, K: int, S: int, prec: str, staged: dict, log=print) -> Tuple[Optional[dict], float, float]:
     """Every fused choice timed once end to end, then the three fastest and
-    the staged pipeline's best tiles in turn over three rounds (medians).
+    the staged pipeline's best tiles in turn over five rounds of ten
+    integrations each (medians).
     Returns the best fused choice (None where the kernel does not cover the
     shape), its median time and the staged median."""
     import torch
@@ -240,11 +241,11 @@ def tune_pipeline(N: int, K: int, S: int, prec: str, staged: dict, log=print) ->
         log(f"  fused {prec} N={N} K={K} {p} {ms:.4f} ms")
     top = [p for p, _ in sorted(first, key=lambda r: r[1])[:3]]
     seen: Dict[str, List[float]] = {}
-    for r in range(3):
+    for r in range(5):
         for p in top:
             seen.setdefault(json.dumps(p, sort_keys=True), []).append(
-                _time_e2e(corr, torch, N, K, S, prec, x, pipeline=p))
-        seen.setdefault("staged", []).append(_time_e2e(corr, torch, N, K, S, prec, x, tiles=staged))
+                _time_e2e(corr, torch, N, K, S, prec, x, pipeline=p, reps=10))
+        seen.setdefault("staged", []).append(_time_e2e(corr, torch, N, K, S, prec, x, tiles=staged, reps=10))
     staged_ms = _median(seen.pop("staged"))
     best = min(((json.loads(k), _median(v)) for k, v in seen.items()), key=lambda r: r[1])
     log(f"  fused {prec} N={N} K={K} best {best[0]} {best[1]:.4f} ms; staged {staged_ms:.4f} ms")
