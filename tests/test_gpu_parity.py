@@ -101,6 +101,36 @@ def test_matrix_core_transform_spectra(K):
         np.testing.assert_array_equal(got[:, :, b], ref[:, :, b].round())
 
 
+@pytest.mark.parametrize("K", [256, 512])
+def test_matrix_core_transform_extreme_samples(K):
+    """The matrix-core transform (fp16 records) on the largest sample
+    magnitudes: all -8, all 7, and 7 / -8 alternating.  Bin 0 is the sum of
+    the samples (-16K, 14K and -K, exact in f16) bit for bit, bin K/2 is
+    exactly zero, and every other bin is zero within the transform's error
+    budget (the split halves of the twiddles leave residues of order 2^-21 of
+    the complex transform's bin 0, K |x[2m] + i x[2m+1]| <= 8 sqrt(2) K)."""
+    N, S = 3, 4
+    print(f"\n[matrix-core transform, extreme samples] K={K}", flush=True)
+    x = torch.full((S, N, 2 * K), -8, dtype=torch.int8)
+    x[:, 1] = 7
+    x[:, 2, 0::2] = 7
+    x[:, 2, 1::2] = -8
+    packed = synth.pack(x).cuda()
+    c = corr.Correlator(N, K, S, precision="fp16")
+    c.process(packed)
+    buf, n = c.debug_read_spectra()
+    assert n == S
+    got = corr.records_to_spectra(buf, corr.CORR_FP16, N, K, S)
+    ref = oracle.spectra(packed.cpu().numpy(), S, N, K)
+    for a, dc in enumerate((-8 * 2 * K, 7 * 2 * K, -K)):
+        np.testing.assert_array_equal(ref[:, a, 0], dc)
+        np.testing.assert_array_equal(got[:, a, 0], dc)
+        np.testing.assert_array_equal(got[:, a, K // 2], 0)
+        rest = np.delete(got[:, a], [0, K // 2], axis=1)
+        assert np.max(np.abs(rest)) <= 2e-6 * 8 * math.sqrt(2) * K * math.log2(2 * K), np.max(np.abs(rest))
+    c.close()
+
+
 def test_fstage_extreme_samples():
     """All -8 and all 7 samples (largest magnitudes): DC = 2K x, other bins 0."""
     N, K, S = 3, 256, 4
