@@ -436,9 +436,10 @@ int launch_x_and_dump(corr_ctx *h, const uint4 *spec, int ntq, int nkb, hipStrea
     xa.regions = h->regions;
     xa.n_diag = h->n_diag;
     const bool half_or_byte = h->prec == kFP16 || h->prec == kINT8;
-    if (h->n_xgroups && half_or_byte && h->rb == 4 && h->n_diag == 4) {
+    if (h->n_xgroups && (half_or_byte || h->prec == kFP32) && h->rb == 4 && h->n_diag == 4) {
         // 16 blocks: one workgroup per channel stages them all in LDS once per
-        // k-block (the three region groups would fetch every block twice)
+        // k-block (the three region groups would fetch every block twice;
+        // fp32's own 4x4 off-diagonal regions run one wave per SIMD)
         HIP_TRY(launch_xchan(h->prec, xa, st), "X-stage launch");
     } else if (h->n_xgroups && half_or_byte) {
         // groups of regions that share blocks stage them in LDS once per

@@ -114,10 +114,11 @@ hipError_t launch_group(const XArgs &a, hipStream_t st) {
     return hipGetLastError();
 }
 
-// Whole-channel groups (16 antenna blocks): eight waves per workgroup, one
-// workgroup per (channel, split), the 16 blocks of a k-block staged once, in
-// a ring of kXChanRing stages (one workgroup per CU would leave LDS for up to
-// eight; depths 3, 4, 6 and 8 measured the same at N = 256).
+// Whole-channel groups (16 antenna blocks; fp32, fp16 and int8): eight waves
+// per workgroup, one workgroup per (channel, split), the 16 blocks of a
+// k-block staged once, in a ring of kXChanRing stages (one workgroup per CU
+// would leave LDS for up to eight; depths 3, 4, 6 and 8 measured the same at
+// N = 256).
 #ifndef X_CHAN_RING
 #define X_CHAN_RING 3
 #endif
@@ -163,7 +164,12 @@ __global__ __launch_bounds__(kXChanWaves * 64, 1) void xchan_kernel(XArgs a) {
     };
     // logical workgroup as in xstage_kernel: neighbouring channels share an XCD
     const int lb = (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
-    x_chan<PREC, kXChanRing>(a, lb, st);
+    if constexpr (PREC == kFP32) {
+        __shared__ float tb[kXChanWaves * 16 * 17];
+        x_chan_f32<kXChanRing>(a, lb, st, tb);
+    } else {
+        x_chan<PREC, kXChanRing>(a, lb, st);
+    }
 }
 
 template <int PREC>
@@ -178,6 +184,7 @@ hipError_t launch_chan(const XArgs &a, hipStream_t st) {
 
 hipError_t launch_xchan(int prec, const XArgs &a, hipStream_t st) {
     switch (prec) {
+        case kFP32: return launch_chan<kFP32>(a, st);
         case kFP16: return launch_chan<kFP16>(a, st);
         case kINT8: return launch_chan<kINT8>(a, st);
     }

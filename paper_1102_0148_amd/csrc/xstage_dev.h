@@ -86,8 +86,9 @@ __device__ __forceinline__ f32x4 mf32(float a, float b, f32x4 acc) {
 // The accumulators of one wavefront's region: RB x RB pairs of 16-antenna
 // blocks (DIAG: the upper triangle of a diagonal region) of one channel, both
 // 16x16 accumulators of every pair in registers.  zero() clears them, run()
-// adds a range of k-blocks of a record buffer laid out as rec_index, store()
-// turns them into (Re, Im) and writes the pairs a <= b < N of a partial row.
+// adds a range of k-blocks of a record buffer laid out as rec_index (add()
+// one k-block whose records are already in registers), store() turns them
+// into (Re, Im) and writes the pairs a <= b < N of a partial row.
 template <int PREC, int RB, bool DIAG>
 struct XRegion {
     typedef typename AccT<PREC>::type acc_t;
@@ -131,7 +132,34 @@ struct XRegion {
                 for (int J = 0; J < RB; ++J) c[J] = rec[(J0 + J) * 16];
             }
         };
-        auto compute = [&](const uint4 *pr, const uint4 *pc) {
+        auto compute = [&](const uint4 *pr, const uint4 *pc) { this->add(pr, pc); };
+        // set i holds k-block kb + i at the top of a round; in step i of a round
+        // set (i + NBUF - 1) mod NBUF, just freed, is loaded with k-block
+        // kb + i + NBUF - 1 (the last one again past the end) and set i is
+        // multiplied
+        uint4 r[NBUF][RB], c[NBUF][RB];
+#pragma unroll
+        for (int i = 0; i < NBUF - 1; ++i)
+            if (kb0 + i < kb1) load(kb0 + i, r[i], c[i]);
+        int kb = kb0;
+#pragma unroll 1
+        for (; kb + NBUF - 1 < kb1; kb += NBUF) {
+#pragma unroll
+            for (int i = 0; i < NBUF; ++i) {
+                load(min(kb + i + NBUF - 1, kb1 - 1), r[(i + NBUF - 1) % NBUF], c[(i + NBUF - 1) % NBUF]);
+                __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the products
+                compute(r[i], c[i]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < NBUF - 1; ++i)
+            if (kb + i < kb1) compute(r[i], c[i]);
+    }
+
+    // One k-block: the row blocks' records pr[RB] (lane: record tq = 4 kb + g
+    // of antenna 16 I + r) and the column blocks' pc[RB] (unused on the
+    // diagonal).
+    __device__ __forceinline__ void add(const uint4 *pr, const uint4 *pc) {
             if constexpr (F3M) {
                 // record = (re t0, re t1, im t0, im t1)
                 float sr[RB][2], dc[RB][2];
@@ -184,28 +212,6 @@ struct XRegion {
                         mma<PREC>(accI[I][J], qr[I], b);
                     }
             }
-        };
-        // set i holds k-block kb + i at the top of a round; in step i of a round
-        // set (i + NBUF - 1) mod NBUF, just freed, is loaded with k-block
-        // kb + i + NBUF - 1 (the last one again past the end) and set i is
-        // multiplied
-        uint4 r[NBUF][RB], c[NBUF][RB];
-#pragma unroll
-        for (int i = 0; i < NBUF - 1; ++i)
-            if (kb0 + i < kb1) load(kb0 + i, r[i], c[i]);
-        int kb = kb0;
-#pragma unroll 1
-        for (; kb + NBUF - 1 < kb1; kb += NBUF) {
-#pragma unroll
-            for (int i = 0; i < NBUF; ++i) {
-                load(min(kb + i + NBUF - 1, kb1 - 1), r[(i + NBUF - 1) % NBUF], c[(i + NBUF - 1) % NBUF]);
-                __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the products
-                compute(r[i], c[i]);
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < NBUF - 1; ++i)
-            if (kb + i < kb1) compute(r[i], c[i]);
     }
 
     // Write the region into partial row obase ([baseline] of one split and
@@ -460,6 +466,59 @@ __device__ __forceinline__ void xc_store(const XArgs &a, int64_t obase, int I0, 
                 }
             }
         }
+}
+
+// fp32 (three-product form) whole-channel groups: the same stages and wave
+// roles, each wave's regions in XRegion accumulators fed from the stage, so
+// every pair is summed in the same order as by the per-wave regions.  The
+// off-diagonal 4x4 regions' 48 accumulators need 460 registers with their
+// own double-buffered loads (one wave per SIMD); fed from LDS, a wave fits
+// in 242, two per SIMD.
+template <int R>
+__device__ __forceinline__ void x_chan_f32(const XArgs &a, int unit, uint4 *const (&st)[R], float *tb) {
+    if (unit >= a.K * a.nsplit) return;  // the whole workgroup
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int f = unit % a.K, sp = unit / a.K;
+    const int kb0 = (int)((int64_t)sp * a.nkb / a.nsplit);
+    const int kb1 = (int)((int64_t)(sp + 1) * a.nkb / a.nsplit);
+    const int64_t obase = ((int64_t)sp * a.K + f) * a.nb;
+    float *tbw = tb + wave * 16 * 17;
+    if (wave < 2) {
+        const int rA = 4 * wave, rB = 4 * wave + 8;
+        XRegion<kFP32, 4, true> A, B;
+        A.zero();
+        B.zero();
+        if (kb0 < kb1)
+            xc_loop(a.spec, a.K, a.a_pad, f, kb0, kb1, wave, st, [&](const uint4 *stg) {
+                uint4 p[4];
+#pragma unroll
+                for (int I = 0; I < 4; ++I) p[I] = stg[(rA + I) * 64 + lane];
+                A.add(p, p);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int I = 0; I < 4; ++I) p[I] = stg[(rB + I) * 64 + lane];
+                B.add(p, p);
+            });
+        A.store(a.partial, obase, a.N, rA, rA, tbw);
+        B.store(a.partial, obase, a.N, rB, rB, tbw);
+    } else {
+        const int o = wave - 2;
+        const int I0 = o < 3 ? 0 : (o < 5 ? 4 : 8);
+        const int J0 = o < 3 ? 4 * (o + 1) : (o < 5 ? 4 * (o - 1) : 12);
+        XRegion<kFP32, 4, false> X;
+        X.zero();
+        if (kb0 < kb1)
+            xc_loop(a.spec, a.K, a.a_pad, f, kb0, kb1, wave, st, [&](const uint4 *stg) {
+                uint4 pr[4], pc[4];
+#pragma unroll
+                for (int I = 0; I < 4; ++I) pr[I] = stg[(I0 + I) * 64 + lane];
+#pragma unroll
+                for (int J = 0; J < 4; ++J) pc[J] = stg[(J0 + J) * 64 + lane];
+                X.add(pr, pc);
+            });
+        X.store(a.partial, obase, a.N, I0, J0, tbw);
+    }
 }
 
 template <int PREC, int R>

@@ -189,14 +189,17 @@ def test_fp32_end_to_end(N, K, S):
         assert np.all(raw[bl, :, 1] == 0.0) and np.all(raw[bl, :, 0] >= 0.0)
 
 
-@pytest.mark.parametrize("N,K,S", [(256, 512, 24), (160, 128, 40)])
-def test_fp32_large_n_regions(N, K, S):
-    """N above 96 uses the multi-region X-stage (diagonal and off-diagonal
-    launches); N = 160 pads to 192 antennas."""
-    print(f"\n[fp32 large N] N={N} K={K} S={S}", flush=True)
+@pytest.mark.parametrize("N,K,S,splits", [(256, 512, 24, 0), (160, 128, 40, 0), (200, 128, 104, 1),
+                                          (256, 128, 104, 3), (193, 256, 40, 2)])
+def test_fp32_large_n_regions(N, K, S, splits):
+    """N above 96 uses the multi-region X-stage: N = 160 (padded to 192)
+    the diagonal and off-diagonal launches, N from 193 to 256 (16 blocks)
+    the whole-channel groups, over k-block ranges that are whole rounds of
+    the ring and ragged ones."""
+    print(f"\n[fp32 large N] N={N} K={K} S={S} splits={splits}", flush=True)
     r = synth.recipe_sources(N=N, two_k=2 * K, seed=4)
     packed = _packed(r, S)
-    c, raw = run(N, K, S, packed)
+    c, raw = run(N, K, S, packed, tiles=dict(x_splits=splits) if splits else None)
     ref = oracle.correlate(packed.cpu().numpy(), S, N, K)
     assert coef_error(raw_to_complex(raw), ref, N) <= TOL[corr.CORR_FP32]
 
