@@ -83,25 +83,27 @@ __device__ __forceinline__ f32x4 mf32(float a, float b, f32x4 acc) {
 }
 
 
-// The accumulators of one wavefront's region: RB x RB pairs of 16-antenna
-// blocks (DIAG: the upper triangle of a diagonal region) of one channel, both
+// The accumulators of one wavefront's region: RB x RBJ pairs of 16-antenna
+// blocks (DIAG: the upper triangle of a square diagonal region) of one
+// channel, both
 // 16x16 accumulators of every pair in registers.  zero() clears them, run()
 // adds a range of k-blocks of a record buffer laid out as rec_index (add()
 // one k-block whose records are already in registers), store() turns them
 // into (Re, Im) and writes the pairs a <= b < N of a partial row.
-template <int PREC, int RB, bool DIAG>
+template <int PREC, int RB, bool DIAG, int RBJ = RB>
 struct XRegion {
+    static_assert(!DIAG || RBJ == RB, "a diagonal region is square");
     typedef typename AccT<PREC>::type acc_t;
     static constexpr bool F3M = PREC == kFP32;  // three-product form
     // Q form: accR = Re, accI = Im.  fp32: diagonal pair accR = Re, accI = M;
     // off-diagonal pair accR = P1, accI = P2, acc3 = P3.
-    acc_t accR[RB][RB], accI[RB][RB], acc3[RB][RB];
+    acc_t accR[RB][RBJ], accI[RB][RBJ], acc3[RB][RBJ];
 
     __device__ __forceinline__ void zero() {
 #pragma unroll
         for (int I = 0; I < RB; ++I)
 #pragma unroll
-            for (int J = 0; J < RB; ++J) {
+            for (int J = 0; J < RBJ; ++J) {
                 accR[I][J] = acc_t{0, 0, 0, 0};
                 accI[I][J] = acc_t{0, 0, 0, 0};
                 acc3[I][J] = acc_t{0, 0, 0, 0};
@@ -129,7 +131,7 @@ struct XRegion {
             for (int I = 0; I < RB; ++I) r[I] = rec[(I0 + I) * 16];
             if constexpr (!DIAG) {
 #pragma unroll
-                for (int J = 0; J < RB; ++J) c[J] = rec[(J0 + J) * 16];
+                for (int J = 0; J < RBJ; ++J) c[J] = rec[(J0 + J) * 16];
             }
         };
         auto compute = [&](const uint4 *pr, const uint4 *pc) { this->add(pr, pc); };
@@ -137,7 +139,7 @@ struct XRegion {
         // set (i + NBUF - 1) mod NBUF, just freed, is loaded with k-block
         // kb + i + NBUF - 1 (the last one again past the end) and set i is
         // multiplied
-        uint4 r[NBUF][RB], c[NBUF][RB];
+        uint4 r[NBUF][RB], c[NBUF][RBJ];
 #pragma unroll
         for (int i = 0; i < NBUF - 1; ++i)
             if (kb0 + i < kb1) load(kb0 + i, r[i], c[i]);
@@ -162,7 +164,7 @@ struct XRegion {
     __device__ __forceinline__ void add(const uint4 *pr, const uint4 *pc) {
             if constexpr (F3M) {
                 // record = (re t0, re t1, im t0, im t1)
-                float sr[RB][2], dc[RB][2];
+                float sr[RB][2], dc[RBJ][2];
 #pragma unroll
                 for (int I = 0; I < RB; ++I) {
                     const float4 p = *reinterpret_cast<const float4 *>(&pr[I]);
@@ -170,7 +172,7 @@ struct XRegion {
                     sr[I][1] = p.y + p.w;
                 }
 #pragma unroll
-                for (int J = 0; J < RB; ++J) {
+                for (int J = 0; J < RBJ; ++J) {
                     const float4 p = *reinterpret_cast<const float4 *>(DIAG ? &pr[J] : &pc[J]);
                     dc[J][0] = p.x - p.z;
                     dc[J][1] = p.y - p.w;
@@ -178,7 +180,7 @@ struct XRegion {
 #pragma unroll
                 for (int I = 0; I < RB; ++I)
 #pragma unroll
-                    for (int J = 0; J < RB; ++J) {
+                    for (int J = 0; J < RBJ; ++J) {
                         if (DIAG && J < I) continue;
                         const float4 x = *reinterpret_cast<const float4 *>(&pr[I]);
                         const float4 y = *reinterpret_cast<const float4 *>(DIAG ? &pr[J] : &pc[J]);
@@ -205,7 +207,7 @@ struct XRegion {
 #pragma unroll
                 for (int I = 0; I < RB; ++I)
 #pragma unroll
-                    for (int J = 0; J < RB; ++J) {
+                    for (int J = 0; J < RBJ; ++J) {
                         if (DIAG && J < I) continue;
                         const uint4 b = DIAG ? pr[J] : pc[J];
                         mma<PREC>(accR[I][J], pr[I], b);
@@ -225,7 +227,7 @@ struct XRegion {
 #pragma unroll
             for (int I = 0; I < RB; ++I)
 #pragma unroll
-                for (int J = 0; J < RB; ++J) {
+                for (int J = 0; J < RBJ; ++J) {
                     if (DIAG && J < I) continue;
                     if (DIAG && I == J) {
 #pragma unroll
@@ -247,7 +249,7 @@ struct XRegion {
 #pragma unroll
         for (int I = 0; I < RB; ++I)
 #pragma unroll
-            for (int J = 0; J < RB; ++J) {
+            for (int J = 0; J < RBJ; ++J) {
                 if (DIAG && J < I) continue;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
@@ -309,24 +311,24 @@ __device__ __forceinline__ void xg_issue(const uint4 *spec, int K, int a_pad, in
 }
 
 // One k-block of a region from a stage: P/Q products as in x_wave.
-template <int PREC, bool DIAG>
+template <int PREC, bool DIAG, int NJ = 4>
 __device__ __forceinline__ void xg_compute(const uint4 *stage, int rs, int cs,
-                                           typename AccT<PREC>::type (&accR)[4][4],
-                                           typename AccT<PREC>::type (&accI)[4][4]) {
+                                           typename AccT<PREC>::type (&accR)[4][NJ],
+                                           typename AccT<PREC>::type (&accI)[4][NJ]) {
     const int lane = threadIdx.x & 63;
-    uint4 pr[4], pc[4], qr[4];
+    uint4 pr[4], pc[NJ], qr[4];
 #pragma unroll
     for (int I = 0; I < 4; ++I) pr[I] = stage[(rs + I) * 64 + lane];
     if constexpr (!DIAG) {
 #pragma unroll
-        for (int J = 0; J < 4; ++J) pc[J] = stage[(cs + J) * 64 + lane];
+        for (int J = 0; J < NJ; ++J) pc[J] = stage[(cs + J) * 64 + lane];
     }
 #pragma unroll
     for (int I = 0; I < 4; ++I) qr[I] = make_q<PREC>(pr[I]);
 #pragma unroll
     for (int I = 0; I < 4; ++I)
 #pragma unroll
-        for (int J = 0; J < 4; ++J) {
+        for (int J = 0; J < NJ; ++J) {
             if (DIAG && J < I) continue;
             const uint4 b = DIAG ? pr[J] : pc[J];
             mma<PREC>(accR[I][J], pr[I], b);
@@ -397,10 +399,15 @@ __device__ __forceinline__ void xg_loop(const uint4 *spec, int K, int a_pad, int
 // workgroup of eight waves per (channel, split) stages all 16 blocks of a
 // k-block in LDS once (slot s = block s; each wave loads two slots), so every
 // record of the channel is fetched once per split instead of twice as with
-// the three region groups.  Waves 2-7 take the six off-diagonal regions
-// (16 block pairs each); waves 0 and 1 take two diagonal regions each
-// (2 x 10 pairs), so with waves dealt to SIMDs in turn the SIMDs carry 36,
-// 36, 32 and 32 block pairs.  Two waves per SIMD keep 256 registers.
+// the three region groups.  The 136 block pairs go to the waves so that
+// every SIMD carries 34 (waves are dealt to SIMDs in turn, w and w + 4
+// sharing one): wave w < 4 takes the diagonal region at block 4w (10 pairs)
+// and half of an off-diagonal one, (0, 4) or (8, 12) split by columns into
+// 4 x 2 blocks (8 pairs); waves 4-7 take the off-diagonal regions (0, 8),
+// (0, 12), (4, 8) and (4, 12) (16 pairs each).  (Two diagonal regions on
+// each of waves 0 and 1 and one off-diagonal region on each other wave left
+// the SIMDs 36, 36, 32 and 32 pairs.)  Two waves per SIMD keep 256
+// registers.
 constexpr int kXChanWaves = 8;
 
 __device__ __forceinline__ void xc_issue(const uint4 *spec, int K, int a_pad, int f, int kb, uint4 *stage, int wave) {
@@ -446,15 +453,15 @@ __device__ __forceinline__ void xc_loop(const uint4 *spec, int K, int a_pad, int
 }
 
 // Writes one region's accumulators as partials (upper triangle, a <= b < N).
-template <int PREC>
+template <int PREC, int NJ = 4>
 __device__ __forceinline__ void xc_store(const XArgs &a, int64_t obase, int I0, int J0, bool dreg,
-                                         typename AccT<PREC>::type (&accR)[4][4],
-                                         typename AccT<PREC>::type (&accI)[4][4]) {
+                                         typename AccT<PREC>::type (&accR)[4][NJ],
+                                         typename AccT<PREC>::type (&accI)[4][NJ]) {
     const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int I = 0; I < 4; ++I)
 #pragma unroll
-        for (int J = 0; J < 4; ++J) {
+        for (int J = 0; J < NJ; ++J) {
             if (dreg && J < I) continue;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
@@ -467,6 +474,11 @@ __device__ __forceinline__ void xc_store(const XArgs &a, int64_t obase, int I0, 
             }
         }
 }
+
+// The off-diagonal half region of wave w < 4 (its first row and column
+// block) and the off-diagonal region of wave w >= 4.
+__device__ __forceinline__ int2 xc_half(int w) { return make_int2(w < 2 ? 0 : 8, (w < 2 ? 4 : 12) + 2 * (w & 1)); }
+__device__ __forceinline__ int2 xc_off(int w) { return make_int2(w < 6 ? 0 : 4, (w & 1) ? 12 : 8); }
 
 // fp32 (three-product form) whole-channel groups: the same stages and wave
 // roles, each wave's regions in XRegion accumulators fed from the stage, so
@@ -484,40 +496,43 @@ __device__ __forceinline__ void x_chan_f32(const XArgs &a, int unit, uint4 *cons
     const int kb1 = (int)((int64_t)(sp + 1) * a.nkb / a.nsplit);
     const int64_t obase = ((int64_t)sp * a.K + f) * a.nb;
     float *tbw = tb + wave * 16 * 17;
-    if (wave < 2) {
-        const int rA = 4 * wave, rB = 4 * wave + 8;
-        XRegion<kFP32, 4, true> A, B;
-        A.zero();
-        B.zero();
+    if (wave < 4) {
+        const int rD = 4 * wave;
+        const int2 h = xc_half(wave);
+        XRegion<kFP32, 4, true> D;
+        XRegion<kFP32, 4, false, 2> H;
+        D.zero();
+        H.zero();
         if (kb0 < kb1)
             xc_loop(a.spec, a.K, a.a_pad, f, kb0, kb1, wave, st, [&](const uint4 *stg) {
-                uint4 p[4];
+                uint4 p[4], q[2];
 #pragma unroll
-                for (int I = 0; I < 4; ++I) p[I] = stg[(rA + I) * 64 + lane];
-                A.add(p, p);
+                for (int I = 0; I < 4; ++I) p[I] = stg[(rD + I) * 64 + lane];
+                D.add(p, p);
+                // one region's operands at a time
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int I = 0; I < 4; ++I) p[I] = stg[(rB + I) * 64 + lane];
-                B.add(p, p);
+                for (int I = 0; I < 4; ++I) p[I] = stg[(h.x + I) * 64 + lane];
+#pragma unroll
+                for (int J = 0; J < 2; ++J) q[J] = stg[(h.y + J) * 64 + lane];
+                H.add(p, q);
             });
-        A.store(a.partial, obase, a.N, rA, rA, tbw);
-        B.store(a.partial, obase, a.N, rB, rB, tbw);
+        D.store(a.partial, obase, a.N, rD, rD, tbw);
+        H.store(a.partial, obase, a.N, h.x, h.y, tbw);
     } else {
-        const int o = wave - 2;
-        const int I0 = o < 3 ? 0 : (o < 5 ? 4 : 8);
-        const int J0 = o < 3 ? 4 * (o + 1) : (o < 5 ? 4 * (o - 1) : 12);
+        const int2 o = xc_off(wave);
         XRegion<kFP32, 4, false> X;
         X.zero();
         if (kb0 < kb1)
             xc_loop(a.spec, a.K, a.a_pad, f, kb0, kb1, wave, st, [&](const uint4 *stg) {
                 uint4 pr[4], pc[4];
 #pragma unroll
-                for (int I = 0; I < 4; ++I) pr[I] = stg[(I0 + I) * 64 + lane];
+                for (int I = 0; I < 4; ++I) pr[I] = stg[(o.x + I) * 64 + lane];
 #pragma unroll
-                for (int J = 0; J < 4; ++J) pc[J] = stg[(J0 + J) * 64 + lane];
+                for (int J = 0; J < 4; ++J) pc[J] = stg[(o.y + J) * 64 + lane];
                 X.add(pr, pc);
             });
-        X.store(a.partial, obase, a.N, I0, J0, tbw);
+        X.store(a.partial, obase, a.N, o.x, o.y, tbw);
     }
 }
 
@@ -532,29 +547,28 @@ __device__ __forceinline__ void x_chan(const XArgs &a, int unit, uint4 *const (&
     const int64_t obase = ((int64_t)sp * a.K + f) * a.nb;
     const uint4 *spec = a.spec;
     const int K = a.K, a_pad = a.a_pad;
-    if (wave < 2) {
-        // diagonal regions at blocks 4w and 4w + 8
-        const int rA = 4 * wave, rB = 4 * wave + 8;
-        acc_t aR[4][4], aI[4][4], bR[4][4], bI[4][4];
+    if (wave < 4) {
+        const int rD = 4 * wave;
+        const int2 h = xc_half(wave);
+        acc_t dR[4][4], dI[4][4], hR[4][2], hI[4][2];
 #pragma unroll
-        for (int I = 0; I < 4; ++I)
+        for (int I = 0; I < 4; ++I) {
 #pragma unroll
-            for (int J = 0; J < 4; ++J) aR[I][J] = aI[I][J] = bR[I][J] = bI[I][J] = acc_t{0, 0, 0, 0};
+            for (int J = 0; J < 4; ++J) dR[I][J] = dI[I][J] = acc_t{0, 0, 0, 0};
+#pragma unroll
+            for (int J = 0; J < 2; ++J) hR[I][J] = hI[I][J] = acc_t{0, 0, 0, 0};
+        }
         if (kb0 < kb1)
             xc_loop(spec, K, a_pad, f, kb0, kb1, wave, st, [&](const uint4 *stg) {
-                xg_compute<PREC, true>(stg, rA, rA, aR, aI);
-                // one region's operands at a time: the two sets of
-                // accumulators leave room for no more
+                xg_compute<PREC, true>(stg, rD, rD, dR, dI);
+                // one region's operands at a time
                 __builtin_amdgcn_sched_barrier(0);
-                xg_compute<PREC, true>(stg, rB, rB, bR, bI);
+                xg_compute<PREC, false, 2>(stg, h.x, h.y, hR, hI);
             });
-        xc_store<PREC>(a, obase, rA, rA, true, aR, aI);
-        xc_store<PREC>(a, obase, rB, rB, true, bR, bI);
+        xc_store<PREC>(a, obase, rD, rD, true, dR, dI);
+        xc_store<PREC, 2>(a, obase, h.x, h.y, false, hR, hI);
     } else {
-        // off-diagonal regions (0,4) (0,8) (0,12) (4,8) (4,12) (8,12)
-        const int o = wave - 2;
-        const int I0 = o < 3 ? 0 : (o < 5 ? 4 : 8);
-        const int J0 = o < 3 ? 4 * (o + 1) : (o < 5 ? 4 * (o - 1) : 12);
+        const int2 o = xc_off(wave);
         acc_t aR[4][4], aI[4][4];
 #pragma unroll
         for (int I = 0; I < 4; ++I)
@@ -562,8 +576,8 @@ __device__ __forceinline__ void x_chan(const XArgs &a, int unit, uint4 *const (&
             for (int J = 0; J < 4; ++J) aR[I][J] = aI[I][J] = acc_t{0, 0, 0, 0};
         if (kb0 < kb1)
             xc_loop(spec, K, a_pad, f, kb0, kb1, wave, st,
-                    [&](const uint4 *stg) { xg_compute<PREC, false>(stg, I0, J0, aR, aI); });
-        xc_store<PREC>(a, obase, I0, J0, false, aR, aI);
+                    [&](const uint4 *stg) { xg_compute<PREC, false>(stg, o.x, o.y, aR, aI); });
+        xc_store<PREC>(a, obase, o.x, o.y, false, aR, aI);
     }
 }
 

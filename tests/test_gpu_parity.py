@@ -204,6 +204,18 @@ def test_fp32_large_n_regions(N, K, S, splits):
     assert coef_error(raw_to_complex(raw), ref, N) <= TOL[corr.CORR_FP32]
 
 
+@pytest.mark.parametrize("N,K,S,splits", [(256, 128, 72, 0), (200, 128, 104, 3)])
+def test_fp16_whole_channel_groups(N, K, S, splits):
+    """fp16 at N from 193 to 256 runs the whole-channel X-stage groups: end
+    to end against the float64 oracle within the fp16 bound, over whole and
+    ragged split ranges."""
+    print(f"\n[fp16 whole-channel] N={N} K={K} S={S} splits={splits}", flush=True)
+    packed = _packed(synth.recipe_sources(N=N, two_k=2 * K, seed=5), S)
+    c, raw = run(N, K, S, packed, precision=corr.CORR_FP16, tiles=dict(x_splits=splits) if splits else None)
+    ref = oracle.correlate(packed.cpu().numpy(), S, N, K)
+    assert coef_error(raw_to_complex(raw), ref, N) <= TOL[corr.CORR_FP16]
+
+
 @pytest.mark.parametrize("tiles", [dict(chunk_spectra=64, x_splits=1, f_group=2),
                                    dict(chunk_spectra=128, x_splits=3, f_group=4),
                                    dict(chunk_spectra=256, x_splits=64, f_group=8)])
